@@ -1,0 +1,229 @@
+/*
+ * ntc.h - C ABI of the MI355X (gfx950) neural BC1 texture decode library.
+ *
+ * Method: Belcour & Benyoub, "Hardware Accelerated Neural Block Texture
+ * Compression with Cooperative Vectors". A material is a pyramid of latent
+ * textures T_k stored as BC1 (Sec. 3.1, latent BC1 compression); a pixel at
+ * coordinate uv is decoded by sampling every T_k bilinearly (Sec. 3.3),
+ * concatenating the colours with uv into x and evaluating a small MLP
+ * f(x) (Sec. 3.1, network architecture). The paper evaluates the MLP on
+ * matrix engines over pixel tiles grouped by MLP (Sec. 4).
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked [device] are HIP device (or managed) memory, [host] are
+ *     host memory read only during the call. The caller owns all memory; the
+ *     library never allocates, frees or synchronises, and never prints.
+ *   - `stream` is a hipStream_t (NULL = the null stream). Work is enqueued on
+ *     it and the call returns without waiting; every launch is
+ *     stream-ordered and contains no memset/memcpy nodes, so it can be
+ *     captured into a HIP graph.
+ *   - Arguments are validated on the host before anything is enqueued; on
+ *     any error nothing is enqueued and a status other than NTC_OK is
+ *     returned (ntc_last_error() then holds a message for this thread).
+ *   - Outputs are fully overwritten. Inputs are never written.
+ *
+ * Feature layout (Sec. 3.1): x = [c_0.rgb, c_1.rgb, ..., c_{K-1}.rgb, u, v],
+ * so dims[0] of every MLP must be 3 * n_levels + 2.
+ * Texel centres sit at (i + 1/2) / W; level k is sampled at
+ * x = u W_k - 1/2 + shift[k][0] texels (likewise y), which realises the
+ * half-texel shift of the second and fourth textures (Sec. 3.1, variants)
+ * when shift = {0, 1/2, 0, 1/2}.
+ * Activations: ReLU on hidden layers, sigmoid on the output layer.
+ */
+#ifndef NTC_H_
+#define NTC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NTC_MAX_LEVELS 4
+#define NTC_MAX_LAYERS 5
+
+typedef enum {
+    NTC_OK = 0,
+    NTC_E_NULL = 1,        /* a required pointer is NULL */
+    NTC_E_SHAPE = 2,       /* inconsistent or out-of-range sizes */
+    NTC_E_UNSUPPORTED = 3, /* valid request that this build does not implement */
+    NTC_E_WORKSPACE = 4,   /* workspace / packed buffer too small */
+    NTC_E_HIP = 5,         /* a HIP launch or runtime call failed */
+    NTC_E_ALIGN = 6        /* a device pointer is not suitably aligned */
+} ntc_status;
+
+/* Arithmetic / storage types. */
+typedef enum { NTC_F32 = 0, NTC_F16 = 1, NTC_BF16 = 2, NTC_FP8_E4M3 = 3 } ntc_dtype;
+
+typedef enum { NTC_LATENT_BC1 = 0, NTC_LATENT_F32 = 1 } ntc_latent_fmt;
+
+typedef enum { NTC_CLAMP = 0, NTC_WRAP = 1 } ntc_address;
+
+/* Latent pyramid (Sec. 3.1). For NTC_LATENT_BC1, data[k] holds
+ * (height[k]/4) x (width[k]/4) little-endian 64-bit BC1 blocks, block-row
+ * major [device, 8-byte aligned]: bits 0-15 endpoint c0 (RGB565: red 11-15,
+ * green 5-10, blue 0-4), bits 16-31 endpoint c1, bits 32-63 the 2-bit index
+ * of texel (x, y) of the block at bit 32 + 2 (4y + x). c0 > c1 selects the
+ * four-colour palette {e0, e1, (2e0+e1)/3, (e0+2e1)/3}, otherwise
+ * {e0, e1, (e0+e1)/2, black} (Khronos BC1, cited in Sec. 3.1).
+ * For NTC_LATENT_F32, data[k] is float [height][width][3] [device, 4-byte
+ * aligned] of continuous latent values. Sizes: 4 <= width, height <= 16384,
+ * multiples of 4 for BC1. */
+typedef struct {
+    int32_t n_levels;              /* 1 .. NTC_MAX_LEVELS */
+    int32_t format;                /* ntc_latent_fmt */
+    int32_t address;               /* ntc_address */
+    int32_t reserved;              /* must be 0 */
+    int32_t width[NTC_MAX_LEVELS];
+    int32_t height[NTC_MAX_LEVELS];
+    float shift[NTC_MAX_LEVELS][2];/* sampling offset in texels, |shift| <= 1 */
+    const void *data[NTC_MAX_LEVELS];
+} ntc_latents;
+
+/* MLP (Sec. 3.1; widths as in Table 1): n_layers linear layers, layer l maps
+ * dims[l] -> dims[l+1]. W[l] is float [dims[l+1]][dims[l]] row-major and
+ * b[l] float [dims[l+1]] [device, FP32 master copy]. Limits: dims[0] =
+ * 3 n_levels + 2 <= 14; 2 <= n_layers <= NTC_MAX_LAYERS; hidden widths all
+ * equal and one of 16, 32, 64; 1 <= dims[n_layers] <= 16. */
+typedef struct {
+    int32_t n_layers;
+    int32_t dims[NTC_MAX_LAYERS + 1];
+    const float *W[NTC_MAX_LAYERS];
+    const float *b[NTC_MAX_LAYERS];
+} ntc_mlp;
+
+/* Tile configuration of the MFMA decode. Zero fields pick defaults.
+ *   waves_per_cu : persistent waves launched per compute unit (1..32)
+ *   tiles_per_iter: 64-pixel tiles a wave stages before running the MLP
+ *                   (only 1 is implemented; reserved for larger tiles)
+ *   stage_capacity: texels a wave may stage in LDS per tile (64..4096);
+ *                   tiles whose footprint is larger fall back to direct
+ *                   block fetches. */
+typedef struct {
+    int32_t waves_per_cu;
+    int32_t tiles_per_iter;
+    int32_t stage_capacity;
+    int32_t reserved;
+} ntc_tile_cfg;
+
+/* Human-readable name of a status code (static string). */
+const char *ntc_status_string(ntc_status s);
+
+/* Detail of the last error returned on this thread (static per-thread
+ * buffer, empty if none). */
+const char *ntc_last_error(void);
+
+/* Library version as 10000 * major + 100 * minor + patch. */
+int32_t ntc_version(void);
+
+/* Bytes of the packed weight image of `mlp` for compute type `compute`
+ * (NTC_F32, NTC_F16 or NTC_FP8_E4M3). [host] */
+ntc_status ntc_mlp_pack_size(const ntc_mlp *mlp, int32_t compute, size_t *bytes);
+
+/* Write the packed weight image used by ntc_decode: weights converted to
+ * `compute`, padded to the matrix-core tile shapes and reordered so that
+ * consecutive layers chain in registers; biases kept in FP32.
+ * For NTC_FP8_E4M3, per-layer scales s_w = 448 / max|W_l| are computed on
+ * the device and act_amax [device, n_layers floats] must hold the largest
+ * |input| of every layer (see ntc_calibrate_fp8); s_a = 448 / act_amax[l].
+ * Otherwise act_amax is ignored. packed [device, 256-byte aligned]. */
+ntc_status ntc_mlp_pack(const ntc_mlp *mlp, int32_t compute, const float *act_amax,
+                        void *packed, size_t bytes, void *stream);
+
+/* FP8 range calibration: act_amax[l] = max over the n samples of |input of
+ * layer l| (the feature vector for l = 0, the ReLU output of layer l-1
+ * otherwise), evaluated with the plain FP32 decode [device, n_layers
+ * floats, overwritten]. packed_f32 is the NTC_F32 image of `mlp` written by
+ * ntc_mlp_pack; uv float [n][2] [device, 8-byte aligned], n >= 1. */
+ntc_status ntc_calibrate_fp8(const ntc_latents *lat, const ntc_mlp *mlp, const void *packed_f32,
+                             const float *uv, int64_t n, float *act_amax, void *stream);
+
+/* Fused decode (Sec. 3.1 + Sec. 3.3 + Sec. 4): out[s] = f(x(uv[s])) for
+ * s < n. compute selects the arithmetic: NTC_F32 (plain FP32 FMAs, one
+ * pixel per lane), NTC_F16 (FP16 matrix cores, FP32 accumulation) or
+ * NTC_FP8_E4M3 (E4M3 matrix cores with per-layer scales, FP32
+ * accumulation). packed is the image written by ntc_mlp_pack for the same
+ * compute type. uv float [n][2] [device, 8-byte aligned]; out [n][C]
+ * with C = dims[n_layers] of out_dtype NTC_F32 or NTC_F16 [device, 16-byte
+ * aligned]. n may be 0 (nothing is enqueued). BC1 latents only for
+ * NTC_F16 / NTC_FP8_E4M3. cfg may be NULL. */
+ntc_status ntc_decode(const ntc_latents *lat, const ntc_mlp *mlp, int32_t compute, const void *packed,
+                      const float *uv, int64_t n, void *out, int32_t out_dtype,
+                      const ntc_tile_cfg *cfg, void *stream);
+
+/* Workspace bytes needed by ntc_decode_backward for these shapes. [host] */
+ntc_status ntc_decode_backward_workspace(const ntc_latents *lat, const ntc_mlp *mlp, int64_t n,
+                                         size_t *bytes);
+
+/* Backward of the FP32 decode (Sec. 3.2: gradients pass through the MLP into
+ * the latent elements) for continuous latents (NTC_LATENT_F32): given
+ * grad_out = dL/dout float [n][C] [device], writes
+ *   grad_W[l] float [dims[l+1]][dims[l]], grad_b[l] float [dims[l+1]],
+ *   grad_latents[k] float [height[k]][width[k]][3]          [all device]
+ * (arrays of n_layers / n_levels device pointers [host]). Activations are
+ * recomputed per tile. Weight gradients are summed per workgroup in FP32 and
+ * across workgroups in FP64; latent gradients are accumulated with FP32
+ * atomics (their summation order is not deterministic). workspace [device,
+ * 256-byte aligned] of at least ntc_decode_backward_workspace bytes. */
+ntc_status ntc_decode_backward(const ntc_latents *lat, const ntc_mlp *mlp, const float *uv, int64_t n,
+                               const float *grad_out, float *const *grad_W, float *const *grad_b,
+                               float *const *grad_latents, void *workspace, size_t ws_bytes,
+                               void *stream);
+
+/* ------------------------------------------------------------------------
+ * Many materials in one launch (Sec. 4: pixels are grouped by MLP so that
+ * a workgroup runs one set of weights; Alg. 1 builds per-MLP tile groups).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    ntc_latents lat;   /* BC1 latents [device] */
+    ntc_mlp mlp;       /* shapes (dims, n_layers); W / b may be NULL */
+    const void *packed;/* NTC_F16 packed image of this material [device] */
+    const float *uv;   /* [n][2] [device] */
+    int64_t n;
+    void *out;         /* [n][C] [device] */
+    int32_t out_dtype; /* NTC_F32 or NTC_F16 */
+    int32_t reserved;
+} ntc_material;
+
+/* Batch options. item_pixels: pixels per work item (multiple of 64,
+ * 64..65536, 0 = 4096); waves_per_cu as in ntc_tile_cfg. */
+typedef struct {
+    int32_t item_pixels;
+    int32_t waves_per_cu;
+    int32_t stage_capacity;
+    int32_t n_cus;      /* compute units to size the grid for (0 = 256) */
+} ntc_batch_cfg;
+
+/* Bytes of the plan image for this batch. [host] */
+ntc_status ntc_batched_plan_size(const ntc_material *mats, int32_t n_mats, const ntc_batch_cfg *cfg,
+                                 size_t *bytes);
+
+/* Build the plan image [host buffer of plan_size bytes]: the material
+ * table and a work list of (material, pixel range) items, grouped by MLP
+ * shape and assigned to persistent waves by longest-processing-time-first
+ * bin packing. The caller copies it to device memory (any 256-byte aligned
+ * buffer) before ntc_decode_batched; device pointers inside are those of
+ * `mats`. */
+ntc_status ntc_batched_plan(const ntc_material *mats, int32_t n_mats, const ntc_batch_cfg *cfg,
+                            void *plan_host, size_t bytes);
+
+/* Decode every material of the plan in one persistent launch. plan_host is
+ * the host image (read for the launch size only), plan_dev its device copy. */
+ntc_status ntc_decode_batched(const void *plan_host, const void *plan_dev, size_t bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Test export: BC1 texel decode of one level (Sec. 3.1 blend).
+ * numer [device, may be NULL] uint16 [H][W][3]: exact numerators of the
+ * channel values over 6 (2^b - 1), i.e. over 186 for red and blue and 378
+ * for green. out [device, may be NULL] float [H][W][3]: the value
+ * numer / denominator rounded once to FP32.
+ * ---------------------------------------------------------------------- */
+ntc_status ntc_bc1_decode_texels(const ntc_latents *lat, int32_t level, float *out, uint16_t *numer,
+                                 void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NTC_H_ */

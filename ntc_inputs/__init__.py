@@ -337,3 +337,22 @@ def make_material(spec: MaterialSpec, bias: str = "zero"):
     lat = bc1_pyramid(s_lat, spec.latent_sizes)
     Ws, bs = xavier_mlp(s_mlp, spec.dims, bias=bias)
     return lat, Ws, bs
+
+
+def pixel_uv_torch(width: int, height: int, order: str = "tiled", device="cuda"):
+    """Pixel-centre uv of every screen pixel as a float32 [W*H][2] torch tensor
+    built on `device` (same values as pixel_uv without jitter)."""
+    import torch
+    n = width * height
+    k = torch.arange(n, dtype=torch.int64, device=device)
+    if order == "rowmajor":
+        x, y = k % width, k // width
+    else:
+        tiles_x = width // TILE
+        t, r = k // (TILE * TILE), k % (TILE * TILE)
+        x = (t % tiles_x) * TILE + r % TILE
+        y = (t // tiles_x) * TILE + r // TILE
+    uv = torch.empty((n, 2), dtype=torch.float32, device=device)
+    uv[:, 0] = ((x.to(torch.float64) + 0.5) / width).to(torch.float32)
+    uv[:, 1] = ((y.to(torch.float64) + 0.5) / height).to(torch.float32)
+    return uv

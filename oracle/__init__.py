@@ -222,6 +222,16 @@ def fp8_scales(Ws, amax_act):
     return w_scale, a_scale
 
 
+def relu_margin(lat: Latents, mlp: Mlp, uv: np.ndarray, threads: int = 0) -> np.ndarray:
+    """Per sample, the smallest |pre-activation| over all hidden units."""
+    uv = np.ascontiguousarray(uv, dtype=np.float64)
+    out = np.empty(uv.shape[0], np.float64)
+    _load().oracle_relu_margin(lat.c, ctypes.c_int32(lat.n), ctypes.c_int32(lat.address), ctypes.byref(mlp.c),
+                               _ptr(uv), ctypes.c_int64(uv.shape[0]), _ptr(out),
+                               ctypes.c_int32(threads or default_threads()))
+    return out
+
+
 def backward(lat: Latents, mlp: Mlp, uv: np.ndarray, grad_out: np.ndarray, threads: int = 0):
     """Gradients of sum(grad_out * p(uv)) w.r.t. W, b and float latent grids.
 

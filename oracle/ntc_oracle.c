@@ -407,6 +407,27 @@ void oracle_backward(const oracle_level *lv, int32_t n_levels, int32_t mode, con
     free(part);
 }
 
+/* Smallest |pre-activation| over the hidden units of every sample: the
+ * distance of the sample from a ReLU kink, where FP32 and FP64 evaluations
+ * may take different derivative branches. */
+void oracle_relu_margin(const oracle_level *lv, int32_t n_levels, int32_t mode, const oracle_mlp *m,
+                        const double *uv, int64_t n, double *margin, int32_t threads) {
+#pragma omp parallel for schedule(dynamic, 256) num_threads(threads > 0 ? threads : 1)
+    for (int64_t s = 0; s < n; ++s) {
+        double x[3 * OR_MAX_LEVELS + 2], z[OR_MAX_LAYERS * OR_MAX_DIM], f[OR_MAX_DIM];
+        features_one(lv, n_levels, mode, uv[2 * s], uv[2 * s + 1], x);
+        mlp_one(m, x, f, z, NULL);
+        double mg = INFINITY;
+        int64_t off = 0;
+        for (int l = 0; l + 1 < m->n_layers; ++l) {
+            for (int k = 0; k < m->dims[l + 1]; ++k)
+                if (fabs(z[off + k]) < mg) mg = fabs(z[off + k]);
+            off += m->dims[l + 1];
+        }
+        margin[s] = mg;
+    }
+}
+
 int32_t oracle_max_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

@@ -1,0 +1,341 @@
+"""Python face of libntc: torch tensors in, torch tensors out.
+
+PyTorch provides device memory and the current stream; every computation is
+one of libntc's HIP kernels, called through the C ABI declared in
+include/ntc.h. Names follow the paper (Belcour & Benyoub): latents T_k
+(Sec. 3.1), the MLP f (Sec. 3.1), the decode p(uv) = f(x(uv)).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi as A
+from ._abi import NtcError, check
+
+PAPER_SHIFT = ((0.0, 0.0), (0.5, 0.5), (0.0, 0.0), (0.5, 0.5))
+NO_SHIFT = ((0.0, 0.0),) * 4
+
+COMPUTE = {"f32": A.F32, "f16": A.F16, "fp8": A.FP8_E4M3}
+OUT_DTYPES = {torch.float32: A.F32, torch.float16: A.F16}
+
+
+def _stream_handle(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _require_cuda(t: torch.Tensor, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Latents:
+    """Latent pyramid T_0..T_{K-1} (Sec. 3.1) on the device.
+
+    levels: BC1 block arrays (int64 / uint64 [(H/4)][(W/4)], the 64-bit block
+    words) or float32 grids [H][W][3]; numpy arrays are copied to `device`.
+    shift: per-level sampling offset in texels (paper: half a texel on the
+    second and fourth textures). address: "clamp" or "wrap".
+    """
+
+    def __init__(self, levels: Sequence, shift=PAPER_SHIFT, address: str = "clamp", device="cuda"):
+        if not 1 <= len(levels) <= A.MAX_LEVELS:
+            raise ValueError("1..4 latent levels")
+        self.tensors: List[torch.Tensor] = []
+        fmt = None
+        sizes = []
+        for lv in levels:
+            if isinstance(lv, np.ndarray):
+                if lv.dtype == np.uint64:
+                    lv = torch.from_numpy(np.ascontiguousarray(lv).view(np.int64))
+                else:
+                    lv = torch.from_numpy(np.ascontiguousarray(lv, dtype=np.float32))
+                lv = lv.to(device)
+            if lv.dtype in (torch.int64, torch.uint64):
+                f = A.LATENT_BC1
+                h, w = lv.shape[0] * 4, lv.shape[1] * 4
+            elif lv.dtype == torch.float32:
+                f = A.LATENT_F32
+                h, w = lv.shape[0], lv.shape[1]
+                if lv.dim() != 3 or lv.shape[2] != 3:
+                    raise ValueError("float latents are [H][W][3]")
+            else:
+                raise ValueError(f"unsupported latent dtype {lv.dtype}")
+            if fmt is not None and f != fmt:
+                raise ValueError("all levels must share one format")
+            fmt = f
+            _require_cuda(lv, "latent level")
+            self.tensors.append(lv)
+            sizes.append((w, h))
+        self.format = fmt
+        self.sizes = sizes
+        self.shift = tuple(tuple(map(float, s)) for s in shift[:len(levels)])
+        self.address = {"clamp": A.CLAMP, "wrap": A.WRAP}[address]
+        c = A.ntc_latents()
+        c.n_levels = len(levels)
+        c.format = fmt
+        c.address = self.address
+        c.reserved = 0
+        for k, t in enumerate(self.tensors):
+            c.width[k], c.height[k] = sizes[k]
+            c.shift[k][0], c.shift[k][1] = self.shift[k]
+            c.data[k] = t.data_ptr()
+        self.c = c
+
+    @property
+    def n_levels(self) -> int:
+        return len(self.tensors)
+
+
+class Mlp:
+    """MLP f (Sec. 3.1): W[l] float32 [dims[l+1]][dims[l]], b[l] float32 [dims[l+1]]."""
+
+    def __init__(self, Ws, bs, device="cuda"):
+        self.W = [torch.as_tensor(np.asarray(w) if isinstance(w, np.ndarray) else w).to(device, torch.float32).contiguous()
+                  for w in Ws]
+        self.b = [torch.as_tensor(np.asarray(b) if isinstance(b, np.ndarray) else b).to(device, torch.float32).contiguous()
+                  for b in bs]
+        if not 2 <= len(self.W) <= A.MAX_LAYERS:
+            raise ValueError("2..5 layers")
+        self.dims = [self.W[0].shape[1]] + [w.shape[0] for w in self.W]
+        c = A.ntc_mlp()
+        c.n_layers = len(self.W)
+        for i, d in enumerate(self.dims):
+            c.dims[i] = d
+        for l in range(len(self.W)):
+            c.W[l] = self.W[l].data_ptr()
+            c.b[l] = self.b[l].data_ptr()
+        self.c = c
+
+    @classmethod
+    def shape_only(cls, dims):
+        m = cls.__new__(cls)
+        m.W, m.b, m.dims = [], [], list(dims)
+        c = A.ntc_mlp()
+        c.n_layers = len(dims) - 1
+        for i, d in enumerate(dims):
+            c.dims[i] = d
+        m.c = c
+        return m
+
+    @property
+    def n_out(self) -> int:
+        return self.dims[-1]
+
+
+def pack_size(mlp: Mlp, compute: str) -> int:
+    n = ctypes.c_size_t(0)
+    check(A.lib().ntc_mlp_pack_size(ctypes.byref(mlp.c), COMPUTE[compute], ctypes.byref(n)))
+    return n.value
+
+
+def pack(mlp: Mlp, compute: str, act_amax: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Packed weight image for `compute` ("f32", "f16" or "fp8")."""
+    nbytes = pack_size(mlp, compute)
+    dev = mlp.W[0].device
+    buf = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    check(A.lib().ntc_mlp_pack(ctypes.byref(mlp.c), COMPUTE[compute], _ptr(act_amax), _ptr(buf),
+                               ctypes.c_size_t(nbytes), _stream_handle()))
+    return buf
+
+
+def calibrate_fp8(lat: Latents, mlp: Mlp, uv: torch.Tensor, packed_f32: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Largest |input| of every layer over the calibration samples uv."""
+    _require_cuda(uv, "uv")
+    if packed_f32 is None:
+        packed_f32 = pack(mlp, "f32")
+    amax = torch.empty(len(mlp.W), dtype=torch.float32, device=uv.device)
+    check(A.lib().ntc_calibrate_fp8(ctypes.byref(lat.c), ctypes.byref(mlp.c), _ptr(packed_f32), _ptr(uv),
+                                    ctypes.c_int64(uv.shape[0]), _ptr(amax), _stream_handle()))
+    return amax
+
+
+def tile_cfg(waves_per_cu: int = 0, stage_capacity: int = 0) -> A.ntc_tile_cfg:
+    c = A.ntc_tile_cfg()
+    c.waves_per_cu = waves_per_cu
+    c.tiles_per_iter = 0
+    c.stage_capacity = stage_capacity
+    c.reserved = 0
+    return c
+
+
+def decode(lat: Latents, mlp: Mlp, uv: torch.Tensor, compute: str = "f16", packed: Optional[torch.Tensor] = None,
+           out_dtype=torch.float32, cfg: Optional[A.ntc_tile_cfg] = None, out: Optional[torch.Tensor] = None,
+           stream=None) -> torch.Tensor:
+    """p(uv) = f(x(uv)) for every row of uv (float32 [n][2]); returns [n][C]."""
+    _require_cuda(uv, "uv")
+    if uv.dtype != torch.float32 or uv.dim() != 2 or uv.shape[1] != 2:
+        raise ValueError("uv must be float32 [n][2]")
+    if packed is None:
+        packed = pack(mlp, compute)
+    n = uv.shape[0]
+    if out is None:
+        out = torch.empty((n, mlp.n_out), dtype=out_dtype, device=uv.device)
+    check(A.lib().ntc_decode(ctypes.byref(lat.c), ctypes.byref(mlp.c), COMPUTE[compute], _ptr(packed), _ptr(uv),
+                             ctypes.c_int64(n), _ptr(out), OUT_DTYPES[out.dtype],
+                             ctypes.byref(cfg) if cfg is not None else None, _stream_handle(stream)))
+    return out
+
+
+def bc1_decode_texels(lat: Latents, level: int):
+    """(value float32 [H][W][3], numerator int32 [H][W][3]) of one BC1 level."""
+    w, h = lat.sizes[level]
+    dev = lat.tensors[level].device
+    val = torch.empty((h, w, 3), dtype=torch.float32, device=dev)
+    num = torch.empty((h, w, 3), dtype=torch.int16, device=dev)
+    check(A.lib().ntc_bc1_decode_texels(ctypes.byref(lat.c), level, _ptr(val), _ptr(num), _stream_handle()))
+    return val, num.to(torch.int32) & 0xFFFF
+
+
+# ---------------------------------------------------------------------------
+# Backward (Sec. 3.2)
+# ---------------------------------------------------------------------------
+def backward_workspace_size(lat: Latents, mlp: Mlp, n: int) -> int:
+    b = ctypes.c_size_t(0)
+    check(A.lib().ntc_decode_backward_workspace(ctypes.byref(lat.c), ctypes.byref(mlp.c), ctypes.c_int64(n),
+                                                 ctypes.byref(b)))
+    return b.value
+
+
+def decode_backward(lat: Latents, mlp: Mlp, uv: torch.Tensor, grad_out: torch.Tensor,
+                    workspace: Optional[torch.Tensor] = None):
+    """Gradients (grad_W list, grad_b list, grad_latents list) of
+    sum(grad_out * p(uv)) for float latents."""
+    _require_cuda(uv, "uv")
+    grad_out = grad_out.contiguous()
+    _require_cuda(grad_out, "grad_out")
+    if grad_out.dtype != torch.float32 or grad_out.shape != (uv.shape[0], mlp.n_out):
+        raise ValueError("grad_out must be float32 [n][C]")
+    n = uv.shape[0]
+    dev = uv.device
+    gW = [torch.empty_like(w) for w in mlp.W]
+    gb = [torch.empty_like(b) for b in mlp.b]
+    gl = [torch.empty_like(t) for t in lat.tensors]
+    nbytes = backward_workspace_size(lat, mlp, n)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    L = len(gW)
+    pW = (ctypes.c_void_p * L)(*[t.data_ptr() for t in gW])
+    pb = (ctypes.c_void_p * L)(*[t.data_ptr() for t in gb])
+    pl = (ctypes.c_void_p * len(gl))(*[t.data_ptr() for t in gl])
+    check(A.lib().ntc_decode_backward(ctypes.byref(lat.c), ctypes.byref(mlp.c), _ptr(uv), ctypes.c_int64(n),
+                                      _ptr(grad_out), pW, pb, pl, _ptr(workspace), ctypes.c_size_t(nbytes),
+                                      _stream_handle()))
+    return gW, gb, gl
+
+
+class NtcDecodeFn(torch.autograd.Function):
+    """out = p(uv) for float latents with the plain FP32 decode; backward by
+    the hand-written gradient kernel. Only the inputs are saved: activations
+    are recomputed per tile in the backward kernel.
+
+    apply(uv, shift, address, n_levels, latent_0..latent_{K-1}, W_0, b_0, ..., W_{L-1}, b_{L-1})
+    """
+
+    @staticmethod
+    def forward(ctx, uv, shift, address, n_levels, *params):
+        lat_t = list(params[:n_levels])
+        wb = params[n_levels:]
+        Ws, bs = list(wb[0::2]), list(wb[1::2])
+        lat = Latents([t.detach().contiguous() for t in lat_t], shift=shift, address=address)
+        mlp = Mlp([w.detach() for w in Ws], [b.detach() for b in bs])
+        out = decode(lat, mlp, uv.detach().contiguous(), compute="f32")
+        ctx.save_for_backward(uv, *params)
+        ctx.meta = (shift, address, n_levels)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        shift, address, n_levels = ctx.meta
+        saved = ctx.saved_tensors
+        uv, params = saved[0], saved[1:]
+        lat_t = list(params[:n_levels])
+        wb = params[n_levels:]
+        lat = Latents([t.detach().contiguous() for t in lat_t], shift=shift, address=address)
+        mlp = Mlp([w.detach() for w in wb[0::2]], [b.detach() for b in wb[1::2]])
+        gW, gb, gl = decode_backward(lat, mlp, uv.detach().contiguous(), grad_out.float())
+        grads = list(gl)
+        for w, b in zip(gW, gb):
+            grads += [w, b]
+        return (None, None, None, None) + tuple(grads)
+
+
+def decode_fn(uv, latents: Sequence[torch.Tensor], Ws: Sequence[torch.Tensor], bs: Sequence[torch.Tensor],
+              shift=PAPER_SHIFT, address: str = "clamp"):
+    """Differentiable decode of float latents (see NtcDecodeFn)."""
+    params = list(latents)
+    for w, b in zip(Ws, bs):
+        params += [w, b]
+    return NtcDecodeFn.apply(uv, tuple(shift[:len(latents)]), address, len(latents), *params)
+
+
+# ---------------------------------------------------------------------------
+# Many materials in one launch (Sec. 4 grouping by MLP)
+# ---------------------------------------------------------------------------
+class Material:
+    """One material of a batch: BC1 latents, its MLP (FP16 image packed on
+    construction), its uv and an output buffer."""
+
+    def __init__(self, lat: Latents, mlp: Mlp, uv: torch.Tensor, out: Optional[torch.Tensor] = None,
+                 out_dtype=torch.float32, packed: Optional[torch.Tensor] = None):
+        _require_cuda(uv, "uv")
+        self.lat, self.mlp, self.uv = lat, mlp, uv
+        self.packed = packed if packed is not None else pack(mlp, "f16")
+        self.out = out if out is not None else torch.empty((uv.shape[0], mlp.n_out), dtype=out_dtype,
+                                                           device=uv.device)
+        c = A.ntc_material()
+        c.lat = lat.c
+        c.mlp = mlp.c
+        c.packed = self.packed.data_ptr()
+        c.uv = uv.data_ptr()
+        c.n = uv.shape[0]
+        c.out = self.out.data_ptr()
+        c.out_dtype = OUT_DTYPES[self.out.dtype]
+        c.reserved = 0
+        self.c = c
+
+
+def batch_cfg(item_pixels: int = 0, waves_per_cu: int = 0, stage_capacity: int = 0, n_cus: int = 0):
+    c = A.ntc_batch_cfg()
+    c.item_pixels, c.waves_per_cu, c.stage_capacity, c.n_cus = item_pixels, waves_per_cu, stage_capacity, n_cus
+    return c
+
+
+class BatchPlan:
+    """Host plan image + its device copy for ntc_decode_batched."""
+
+    def __init__(self, materials: Sequence[Material], cfg=None, device="cuda"):
+        self.materials = list(materials)
+        arr = (A.ntc_material * len(self.materials))(*[m.c for m in self.materials])
+        self._arr = arr
+        self.cfg = cfg if cfg is not None else batch_cfg(n_cus=_device_cus(device))
+        n = ctypes.c_size_t(0)
+        check(A.lib().ntc_batched_plan_size(arr, len(self.materials), ctypes.byref(self.cfg), ctypes.byref(n)))
+        self.nbytes = n.value
+        self.host = np.zeros(self.nbytes, dtype=np.uint8)
+        check(A.lib().ntc_batched_plan(arr, len(self.materials), ctypes.byref(self.cfg),
+                                       self.host.ctypes.data_as(ctypes.c_void_p), ctypes.c_size_t(self.nbytes)))
+        self.dev = torch.from_numpy(self.host).to(device)
+        torch.cuda.synchronize(device)
+
+    def header(self):
+        h = self.host[:64].view(np.int32)
+        return dict(n_mats=int(h[2]), n_items=int(h[3]), n_waves=int(h[4]), stage_cap=int(h[5]))
+
+    def launch(self, stream=None):
+        check(A.lib().ntc_decode_batched(self.host.ctypes.data_as(ctypes.c_void_p), _ptr(self.dev),
+                                         ctypes.c_size_t(self.nbytes), _stream_handle(stream)))
+
+
+def _device_cus(device="cuda") -> int:
+    return torch.cuda.get_device_properties(torch.device(device)).multi_processor_count

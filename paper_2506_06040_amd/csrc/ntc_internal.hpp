@@ -1,0 +1,139 @@
+// Internal interfaces between the C-ABI layer (ntc_api.hip) and the kernel
+// translation units. Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ntc_device.hpp"
+
+namespace ntc {
+
+// Shape summary of an MLP accepted by the library.
+struct MlpShape {
+  int32_t n_layers;  // linear layers, 2..kMaxLayers
+  int32_t in_dim;    // 3 * n_levels + 2
+  int32_t hid;       // common hidden width: 16, 32 or 64
+  int32_t n_out;     // 1..16
+};
+
+// ---------------------------------------------------------------------------
+// Packed weight images (written by the pack kernels, read by the decoders).
+//
+// FP32 (plain decode): per layer, W padded to [rows_pad][cols_pad] followed
+// by b[rows_pad]; layer 0 has cols_pad = 16, the last layer rows_pad = 16.
+//
+// Matrix-core images (FP16 / FP8): for every layer a run of A-operand
+// fragments [m][c][lane][e] (M-tile m of 16 output rows, K-chunk c of 32
+// inputs, 64 lanes, 8 elements of 2 or 1 bytes per lane), then bias
+// fragments [m][group][4] floats, then (FP8) two floats per layer:
+// the input scale s_a and the epilogue scale.
+// ---------------------------------------------------------------------------
+struct PackLayout {
+  size_t total;
+  uint32_t w_off[kMaxLayers];     // bytes
+  uint32_t b_off[kMaxLayers];     // bytes
+  uint32_t scale_off;             // bytes (FP8 only)
+  int32_t mt[kMaxLayers];         // M-tiles per layer
+  int32_t kc[kMaxLayers];         // K-chunks per layer
+  int32_t rows_pad[kMaxLayers];   // FP32 image
+  int32_t cols_pad[kMaxLayers];   // FP32 image
+  int32_t elem_bytes;             // 4 (FP32), 2 (FP16), 1 (FP8)
+};
+
+PackLayout pack_layout(const MlpShape &s, int compute);
+
+struct MlpPtrs {
+  const float *W[kMaxLayers];
+  const float *b[kMaxLayers];
+  int32_t dims[kMaxLayers + 1];
+};
+
+hipError_t launch_pack(const MlpShape &s, const MlpPtrs &p, int compute, const float *act_amax,
+                       uint8_t *packed, const PackLayout &lay, hipStream_t st);
+
+// Arguments of the decode kernels.
+struct DecodeArgs {
+  LatArgs lat;
+  const uint8_t *packed;
+  const float2 *uv;
+  void *out;
+  int64_t n;
+  int64_t n_tiles;      // ceil(n / 64)
+  int32_t n_out;
+  int32_t out_f16;
+  int32_t stage_cap;    // texels per wave in LDS
+  int32_t n_layers;
+  PackLayout lay;
+};
+
+hipError_t launch_decode_plain(const DecodeArgs &a, const MlpShape &s, float *calib_amax, int n_cus,
+                               hipStream_t st);
+hipError_t launch_decode_mfma(const DecodeArgs &a, const MlpShape &s, int compute, int grid_waves,
+                              hipStream_t st);
+hipError_t launch_bc1_texels(const LevelArgs &L, float *out, uint16_t *numer, hipStream_t st);
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
+
+// Backward.
+struct BackwardArgs {
+  LatArgs lat;
+  const float *W[kMaxLayers];
+  const float *b[kMaxLayers];
+  const float2 *uv;
+  const float *grad_out;
+  float *grad_lat[kMaxLevels];
+  float *wpart;          // [n_blocks][n_params] FP32 per-block partial sums
+  int64_t n;
+  int32_t n_params;
+  int32_t n_blocks;
+  int32_t dims[kMaxLayers + 1];
+  int32_t n_layers;
+};
+size_t backward_workspace_bytes(const MlpShape &s, int n_blocks);
+int backward_blocks(int64_t n);
+int backward_n_params(const MlpShape &s);
+hipError_t launch_backward(const BackwardArgs &a, const MlpShape &s, float *const *grad_W,
+                           float *const *grad_b, hipStream_t st);
+
+// Many materials in one launch.
+struct BatchMaterial {
+  DecodeArgs a;       // decode arguments of the material (FP16 image)
+  int32_t shape_id;   // 3 * log2(hid / 16) + (n_layers - 2)
+  int32_t hid;
+  int32_t n_layers;
+  int32_t pad_;
+};
+
+struct BatchItem {
+  int32_t mat;
+  int32_t shape_id;
+  int64_t first_tile;
+  int64_t n_tiles;
+};
+
+struct BatchPlanHeader {
+  uint32_t magic;
+  uint32_t version;
+  int32_t n_mats;
+  int32_t n_items;
+  int32_t n_waves;
+  int32_t stage_cap;
+  uint64_t mats_off;        // bytes from plan start
+  uint64_t items_off;
+  uint64_t wave_start_off;  // int32 [n_waves + 1]: items of wave w are [start[w], start[w+1])
+  uint64_t total_bytes;
+};
+
+constexpr uint32_t kPlanMagic = 0x4E544350u;  // "NTCP"
+constexpr uint32_t kPlanVersion = 1;
+
+hipError_t launch_decode_batched(const uint8_t *plan_dev, const BatchPlanHeader &h, hipStream_t st);
+int shape_id_of(int hid, int n_layers);
+size_t plan_bytes(int n_mats, int64_t n_items, int n_waves);
+int64_t count_items(const int64_t *n_px, int n_mats, int item_tiles);
+int plan_waves(int64_t n_items, int n_cus, int waves_per_cu);
+void build_plan(const BatchMaterial *mats, int n_mats, int item_tiles, int n_waves, int stage_cap, uint8_t *out,
+                size_t bytes);
+
+}  // namespace ntc

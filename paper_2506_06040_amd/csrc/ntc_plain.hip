@@ -1,0 +1,401 @@
+// Plain FP32 decode (one pixel per lane, scalar FMAs: the analogue of the
+// paper's "software FMA" path of Table 2), the FP8 range calibration that
+// shares it, the BC1 texel export, small fill kernels and the weight
+// packers.
+#include <hip/hip_runtime.h>
+
+#include "ntc_device.hpp"
+#include "ntc_internal.hpp"
+
+namespace ntc {
+
+// ---------------------------------------------------------------------------
+// Packed layouts
+// ---------------------------------------------------------------------------
+static inline uint32_t align_up(size_t v, size_t a) { return (uint32_t)((v + a - 1) / a * a); }
+
+PackLayout pack_layout(const MlpShape &s, int compute) {
+  PackLayout L{};
+  size_t off = 0;
+  const int Ln = s.n_layers;
+  if (compute == 0) {  // FP32
+    L.elem_bytes = 4;
+    for (int l = 0; l < Ln; ++l) {
+      const int rows = (l == Ln - 1) ? 16 : s.hid;
+      const int cols = (l == 0) ? 16 : s.hid;
+      L.rows_pad[l] = rows;
+      L.cols_pad[l] = cols;
+      L.w_off[l] = align_up(off, 256);
+      off = L.w_off[l] + (size_t)rows * cols * 4;
+      L.b_off[l] = align_up(off, 256);
+      off = L.b_off[l] + (size_t)rows * 4;
+    }
+  } else {
+    L.elem_bytes = (compute == 3) ? 1 : 2;
+    const size_t frag = 64 * 8 * (size_t)L.elem_bytes;
+    for (int l = 0; l < Ln; ++l) {
+      L.mt[l] = (l == Ln - 1) ? 1 : s.hid / 16;
+      L.kc[l] = (l == 0) ? 1 : (s.hid >= 32 ? s.hid / 32 : 1);
+      L.w_off[l] = align_up(off, 256);
+      off = L.w_off[l] + (size_t)L.mt[l] * L.kc[l] * frag;
+      L.b_off[l] = align_up(off, 256);
+      off = L.b_off[l] + (size_t)L.mt[l] * 64;
+    }
+  }
+  L.scale_off = align_up(off, 256);
+  off = L.scale_off + 4 * kMaxLayers * sizeof(float);
+  L.total = align_up(off, 256);
+  return L;
+}
+
+struct PackArgs {
+  MlpPtrs p;
+  MlpShape s;
+  PackLayout lay;
+  const float *act_amax;
+  uint8_t *packed;
+  int compute;
+};
+
+// Source column of element e (0..7) of lane group g in K-chunk c of layer l
+// of a matrix-core image, or -1 for padding.
+//   layer 0: lane group g carries level g (3 channels); group 0 also u, v.
+//   layer >0: the K order follows the accumulator layout of the previous
+//   layer: element e of group g in chunk c is hidden unit
+//   16 (2c + e/4) + 4g + e%4.
+__device__ __forceinline__ int frag_source_col(const MlpShape &s, int l, int c, int g, int e) {
+  if (l == 0) {
+    const int n_levels = (s.in_dim - 2) / 3;
+    if (e < 3) return g < n_levels ? 3 * g + e : -1;
+    if (g == 0 && e == 3) return 3 * n_levels;
+    if (g == 0 && e == 4) return 3 * n_levels + 1;
+    return -1;
+  }
+  const int h = 16 * (2 * c + (e >> 2)) + 4 * g + (e & 3);
+  return h < s.hid ? h : -1;
+}
+
+// Scales of the E4M3 image: s_w = 448 / max|W_l|, s_a = 448 / act_amax[l];
+// stored per layer as (s_a, epilogue, s_w). The epilogue scale maps the
+// accumulator of layer l to the scaled input of layer l + 1
+// (s_a(l+1) / (s_w s_a)) or, for the last layer, to the pre-activation
+// (1 / (s_w s_a)).
+__global__ void pack_scales_kernel(PackArgs a) {
+  const int l = blockIdx.x;
+  const int rows = a.p.dims[l + 1], cols = a.p.dims[l];
+  float m = 0.f;
+  for (int i = threadIdx.x; i < rows * cols; i += blockDim.x) m = fmaxf(m, fabsf(a.p.W[l][i]));
+  __shared__ float red[256];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float wm = red[0];
+    const float sw = wm > 0.f ? 448.0f / wm : 1.0f;
+    const float am = a.act_amax[l];
+    const float sa = am > 0.f ? 448.0f / am : 1.0f;
+    float epi;
+    if (l + 1 < a.s.n_layers) {
+      const float am2 = a.act_amax[l + 1];
+      const float sa2 = am2 > 0.f ? 448.0f / am2 : 1.0f;
+      epi = sa2 / (sw * sa);
+    } else {
+      epi = 1.0f / (sw * sa);
+    }
+    float *sc = (float *)(a.packed + a.lay.scale_off);
+    sc[3 * l + 0] = sa;
+    sc[3 * l + 1] = epi;
+    sc[3 * l + 2] = sw;
+  }
+}
+
+__device__ __forceinline__ uint8_t to_e4m3(float v) {
+  v = fminf(fmaxf(v, -448.0f), 448.0f);
+  return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xFF);
+}
+
+// One thread per element of the image (weights, then biases).
+__global__ void pack_kernel(PackArgs a, int64_t n_w_elems, int64_t n_elems) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_elems) return;
+  const MlpShape &s = a.s;
+  const PackLayout &L = a.lay;
+  const int Ln = s.n_layers;
+  const float *sc = (const float *)(a.packed + L.scale_off);
+  if (a.compute == 0) {
+    // FP32 image: walk layers
+    int64_t r = e;
+    for (int l = 0; l < Ln; ++l) {
+      const int64_t nw = (int64_t)L.rows_pad[l] * L.cols_pad[l];
+      const int64_t nb = L.rows_pad[l];
+      const int rows = a.p.dims[l + 1], cols = a.p.dims[l];
+      if (r < nw) {
+        const int row = (int)(r / L.cols_pad[l]), col = (int)(r % L.cols_pad[l]);
+        float v = 0.f;
+        if (row < rows && col < cols) v = a.p.W[l][(int64_t)row * cols + col];
+        ((float *)(a.packed + L.w_off[l]))[r] = v;
+        return;
+      }
+      r -= nw;
+      if (r < nb) {
+        const int row = (int)r;
+        ((float *)(a.packed + L.b_off[l]))[r] = row < rows ? a.p.b[l][row] : 0.f;
+        return;
+      }
+      r -= nb;
+    }
+    return;
+  }
+  if (e < n_w_elems) {
+    int64_t r = e;
+    for (int l = 0; l < Ln; ++l) {
+      const int64_t nl = (int64_t)L.mt[l] * L.kc[l] * 64 * 8;
+      if (r < nl) {
+        const int el = (int)(r & 7);
+        const int lane = (int)((r >> 3) & 63);
+        const int64_t fr = r >> 9;  // frag index = m * kc + c
+        const int c = (int)(fr % L.kc[l]), m = (int)(fr / L.kc[l]);
+        const int row = 16 * m + (lane & 15);
+        const int col = frag_source_col(s, l, c, lane >> 4, el);
+        const int rows = a.p.dims[l + 1], cols = a.p.dims[l];
+        float v = 0.f;
+        if (row < rows && col >= 0 && col < cols) v = a.p.W[l][(int64_t)row * cols + col];
+        if (a.compute == 3) {
+          (a.packed + L.w_off[l])[r] = to_e4m3(v * sc[3 * l + 2]);
+        } else {
+          ((_Float16 *)(a.packed + L.w_off[l]))[r] = (_Float16)v;
+        }
+        return;
+      }
+      r -= nl;
+    }
+    return;
+  }
+  // bias fragments: [m][group][4] floats
+  int64_t r = e - n_w_elems;
+  for (int l = 0; l < Ln; ++l) {
+    const int64_t nb = (int64_t)L.mt[l] * 16;
+    if (r < nb) {
+      const int m = (int)(r / 16), gi = (int)((r / 4) & 3), ri = (int)(r & 3);
+      const int row = 16 * m + 4 * gi + ri;
+      const int rows = a.p.dims[l + 1];
+      float v = row < rows ? a.p.b[l][row] : 0.f;
+      if (a.compute == 3) v = v * (sc[3 * l + 2] * sc[3 * l + 0]);
+      ((float *)(a.packed + L.b_off[l]))[r] = v;
+      return;
+    }
+    r -= nb;
+  }
+}
+
+hipError_t launch_pack(const MlpShape &s, const MlpPtrs &p, int compute, const float *act_amax,
+                       uint8_t *packed, const PackLayout &lay, hipStream_t st) {
+  PackArgs a;
+  a.p = p;
+  a.s = s;
+  a.lay = lay;
+  a.act_amax = act_amax;
+  a.packed = packed;
+  a.compute = compute;
+  int64_t n_w = 0, n_all = 0;
+  if (compute == 0) {
+    for (int l = 0; l < s.n_layers; ++l) n_all += (int64_t)lay.rows_pad[l] * lay.cols_pad[l] + lay.rows_pad[l];
+    n_w = n_all;
+  } else {
+    for (int l = 0; l < s.n_layers; ++l) n_w += (int64_t)lay.mt[l] * lay.kc[l] * 64 * 8;
+    n_all = n_w;
+    for (int l = 0; l < s.n_layers; ++l) n_all += (int64_t)lay.mt[l] * 16;
+  }
+  if (compute == 3) {
+    hipLaunchKernelGGL(pack_scales_kernel, dim3(s.n_layers), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int bs = 256;
+  const int64_t grid = (n_all + bs - 1) / bs;
+  hipLaunchKernelGGL(pack_kernel, dim3((unsigned)grid), dim3(bs), 0, st, a, n_w, n_all);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Plain FP32 decode
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void atomic_max_nonneg(float *addr, float v) {
+  // non-negative IEEE floats order like their bit patterns
+  atomicMax(reinterpret_cast<unsigned int *>(addr), __float_as_uint(v));
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int HID, bool CALIB>
+__global__ __launch_bounds__(256) void decode_plain_kernel(DecodeArgs a, float *__restrict__ amax) {
+  const float *__restrict__ wp = reinterpret_cast<const float *>(a.packed);
+  const int n_levels = a.lat.n_levels;
+  const int n_layers = a.n_layers;
+  const int n_out = a.n_out;
+  float am[kMaxLayers];
+#pragma unroll
+  for (int l = 0; l < kMaxLayers; ++l) am[l] = 0.f;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.n; p += stride) {
+    const float2 uv = a.uv[p];
+    float x[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = 0.f;
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k) {
+      if (k < n_levels) {
+        const float3 c = sample_level(a.lat, k, uv.x, uv.y);
+        x[3 * k] = c.x;
+        x[3 * k + 1] = c.y;
+        x[3 * k + 2] = c.z;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      if (k == 3 * n_levels) x[k] = uv.x;
+      if (k == 3 * n_levels + 1) x[k] = uv.y;
+    }
+    if (CALIB) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) am[0] = fmaxf(am[0], fabsf(x[k]));
+    }
+    float h[HID];
+    {
+      const float *W = wp + a.lay.w_off[0] / 4;
+      const float *b = wp + a.lay.b_off[0] / 4;
+#pragma unroll
+      for (int o = 0; o < HID; ++o) {
+        float acc = b[o];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc = fmaf(W[o * 16 + k], x[k], acc);
+        h[o] = fmaxf(acc, 0.f);
+      }
+    }
+    for (int l = 1; l < n_layers - 1; ++l) {
+      if (CALIB) {
+#pragma unroll
+        for (int k = 0; k < HID; ++k) am[l] = fmaxf(am[l], h[k]);
+      }
+      const float *W = wp + a.lay.w_off[l] / 4;
+      const float *b = wp + a.lay.b_off[l] / 4;
+      float h2[HID];
+#pragma unroll
+      for (int o = 0; o < HID; ++o) {
+        float acc = b[o];
+#pragma unroll
+        for (int k = 0; k < HID; ++k) acc = fmaf(W[o * HID + k], h[k], acc);
+        h2[o] = fmaxf(acc, 0.f);
+      }
+#pragma unroll
+      for (int o = 0; o < HID; ++o) h[o] = h2[o];
+    }
+    if (CALIB) {
+#pragma unroll
+      for (int k = 0; k < HID; ++k) am[n_layers - 1] = fmaxf(am[n_layers - 1], h[k]);
+      continue;  // calibration only needs the layer inputs
+    }
+    const float *W = wp + a.lay.w_off[n_layers - 1] / 4;
+    const float *b = wp + a.lay.b_off[n_layers - 1] / 4;
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+      if (o < n_out) {
+        float acc = b[o];
+#pragma unroll
+        for (int k = 0; k < HID; ++k) acc = fmaf(W[o * HID + k], h[k], acc);
+        const float f = 1.0f / (1.0f + expf(-acc));
+        if (a.out_f16)
+          reinterpret_cast<_Float16 *>(a.out)[p * n_out + o] = (_Float16)f;
+        else
+          reinterpret_cast<float *>(a.out)[p * n_out + o] = f;
+      }
+    }
+  }
+  if (CALIB) {
+#pragma unroll
+    for (int l = 0; l < kMaxLayers; ++l) {
+      if (l < n_layers) {
+        const float m = wave_max(am[l]);
+        if ((threadIdx.x & 63) == 0) atomic_max_nonneg(amax + l, m);
+      }
+    }
+  }
+}
+
+template <int HID>
+static hipError_t launch_plain_hid(const DecodeArgs &a, float *calib, int n_cus, hipStream_t st) {
+  const int bs = 256;
+  int64_t blocks = (a.n + bs - 1) / bs;
+  const int64_t cap = (int64_t)n_cus * 16;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  if (calib)
+    hipLaunchKernelGGL((decode_plain_kernel<HID, true>), dim3((unsigned)blocks), dim3(bs), 0, st, a, calib);
+  else
+    hipLaunchKernelGGL((decode_plain_kernel<HID, false>), dim3((unsigned)blocks), dim3(bs), 0, st, a, calib);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_plain(const DecodeArgs &a, const MlpShape &s, float *calib_amax, int n_cus,
+                               hipStream_t st) {
+  switch (s.hid) {
+    case 16: return launch_plain_hid<16>(a, calib_amax, n_cus, st);
+    case 32: return launch_plain_hid<32>(a, calib_amax, n_cus, st);
+    case 64: return launch_plain_hid<64>(a, calib_amax, n_cus, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BC1 texel export and fills
+// ---------------------------------------------------------------------------
+__global__ void bc1_texels_kernel(LevelArgs L, float *out, uint16_t *numer) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)L.w * L.h;
+  if (t >= n) return;
+  const int i = (int)(t % L.w), j = (int)(t / L.w);
+  const uint32_t p = bc1_texel_global(L, i, j);
+  const uint32_t nr = p & 255u, nb = (p >> 8) & 255u, ng = p >> 16;
+  if (numer) {
+    numer[t * 3 + 0] = (uint16_t)nr;
+    numer[t * 3 + 1] = (uint16_t)ng;
+    numer[t * 3 + 2] = (uint16_t)nb;
+  }
+  if (out) {
+    // one rounding of the exact quotient (the double quotient of these small
+    // integers is never a float32 rounding tie, so no double rounding)
+    out[t * 3 + 0] = (float)((double)nr / 186.0);
+    out[t * 3 + 1] = (float)((double)ng / 378.0);
+    out[t * 3 + 2] = (float)((double)nb / 186.0);
+  }
+}
+
+hipError_t launch_bc1_texels(const LevelArgs &L, float *out, uint16_t *numer, hipStream_t st) {
+  const int64_t n = (int64_t)L.w * L.h;
+  const int bs = 256;
+  hipLaunchKernelGGL(bc1_texels_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, L, out, numer);
+  return hipGetLastError();
+}
+
+__global__ void fill_f32_kernel(float *p, int64_t n, float v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int bs = 256;
+  int64_t blocks = (n + bs - 1) / bs;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)blocks), dim3(bs), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace ntc

@@ -1,0 +1,169 @@
+"""GPU backward (Sec. 3.2) against the FP64 oracle's analytic gradient and
+central finite differences of the oracle loss (h = 1e-3).
+
+Where floating point takes a branch (the ReLU derivative), the FP32 kernel
+and the FP64 oracle can disagree for samples whose pre-activation lies
+within rounding distance of zero. Those samples are identified by the
+oracle (smallest |pre-activation| below 1e-4) and given a zero upstream
+gradient on both sides, so every remaining contribution is unique; the
+ambiguous samples are at most a few per million.
+"""
+import numpy as np
+import pytest
+import torch
+
+import ntc_inputs as I
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = 1e-4
+
+
+def _ntc():
+    import paper_2506_06040_amd as ntc
+    return ntc
+
+
+def _close(name, got, ref, rtol=1e-4):
+    scale = np.max(np.abs(ref)) + 1e-30
+    err = np.max(np.abs(got - ref)) / scale
+    print(f"[{name}] max |err| / max |ref| = {err:.2e}", flush=True)
+    assert err <= rtol, name
+
+
+def _gpu_autograd(lat_np, Ws, bs, uv, tgt, shift):
+    ntc = _ntc()
+    lat_t = [torch.from_numpy(a).cuda().requires_grad_(True) for a in lat_np]
+    W_t = [torch.from_numpy(w).cuda().requires_grad_(True) for w in Ws]
+    b_t = [torch.from_numpy(b).cuda().requires_grad_(True) for b in bs]
+    out = ntc.decode_fn(torch.from_numpy(uv).cuda(), lat_t, W_t, b_t, shift=shift)
+    loss = torch.mean((out - torch.from_numpy(tgt).cuda()) ** 2)
+    loss.backward()
+    return ([t.grad.cpu().numpy() for t in W_t], [t.grad.cpu().numpy() for t in b_t],
+            [t.grad.cpu().numpy() for t in lat_t], out.detach().cpu().numpy())
+
+
+def _gpu_direct(lat_np, Ws, bs, uv, g, shift):
+    ntc = _ntc()
+    lat = ntc.Latents(lat_np, shift=shift)
+    mlp = ntc.Mlp(Ws, bs)
+    gW, gb, gl = ntc.decode_backward(lat, mlp, torch.from_numpy(uv).cuda(),
+                                     torch.from_numpy(g.astype(np.float32)).cuda())
+    return [t.cpu().numpy() for t in gW], [t.cpu().numpy() for t in gb], [t.cpu().numpy() for t in gl]
+
+
+def test_backward_autograd_small():
+    rng = np.random.default_rng(31)
+    sizes = [(64, 64), (32, 32), (16, 16), (8, 8)]
+    lat_np = I.f32_pyramid(rng, sizes)
+    Ws, bs = I.xavier_mlp(rng, (14, 64, 64, 8), bias="normal")
+    uv = I.random_uv(rng, 4099)
+    olat, omlp = O.Latents(lat_np, shift=I.PAPER_SHIFT), O.Mlp(Ws, bs)
+    keep = O.relu_margin(olat, omlp, uv) >= MARGIN
+    uv = uv[keep]
+    tgt = rng.random((uv.shape[0], 8)).astype(np.float32)
+    gW, gb, gl, f = _gpu_autograd(lat_np, Ws, bs, uv, tgt, I.PAPER_SHIFT)
+    of = O.decode(olat, omlp, uv)
+    assert np.all(np.abs(f - of) <= 1e-5 * np.abs(of))
+    oW, ob, ol = O.backward(olat, omlp, uv, 2.0 * (of - tgt) / of.size)
+    for l in range(3):
+        _close(f"dW{l}", gW[l], oW[l])
+        _close(f"db{l}", gb[l], ob[l])
+    for k in range(4):
+        _close(f"dlat{k}", gl[k], ol[k])
+
+
+@pytest.fixture(scope="module")
+def c3():
+    wl = I.WORKLOADS["c3"]
+    lat_np, Ws, bs, uv = I.make_workload(wl)
+    tgt = I.point_sample(I.c3_targets(), uv)
+    olat, omlp = O.Latents(lat_np, shift=wl.shift), O.Mlp(Ws, bs)
+    margin = O.relu_margin(olat, omlp, uv)
+    return dict(wl=wl, lat_np=lat_np, Ws=Ws, bs=bs, uv=uv, tgt=tgt, olat=olat, omlp=omlp, margin=margin)
+
+
+def test_backward_c3_full_size(c3):
+    """2^20 samples, latents 1024^2..128^2, MLP 14-64-64-8: the same upstream
+    gradient of the L2 loss on both sides (zero on ambiguous samples)."""
+    uv, tgt = c3["uv"], c3["tgt"]
+    f = O.decode(c3["olat"], c3["omlp"], uv)
+    g = (2.0 * (f - tgt) / f.size).astype(np.float32).astype(np.float64)
+    amb = c3["margin"] < MARGIN
+    print(f"[c3] ambiguous samples: {int(amb.sum())} of {uv.shape[0]}", flush=True)
+    g[amb] = 0.0
+    gW, gb, gl = _gpu_direct(c3["lat_np"], c3["Ws"], c3["bs"], uv, g, c3["wl"].shift)
+    oW, ob, ol = O.backward(c3["olat"], c3["omlp"], uv, g)
+    for l in range(3):
+        _close(f"c3 dW{l}", gW[l], oW[l])
+        _close(f"c3 db{l}", gb[l], ob[l])
+    for k in range(4):
+        _close(f"c3 dlat{k}", gl[k], ol[k])
+
+
+def test_backward_c3_finite_differences(c3):
+    """Central differences (h = 1e-3) of the FP64 oracle loss on 64 random
+    parameters (weights, biases, touched latent texels) of the C3 shapes,
+    against the GPU gradient from the autograd path, on 16384 of the samples."""
+    rng = np.random.default_rng(33)
+    sel = np.sort(rng.choice(c3["uv"].shape[0], 16384, replace=False))
+    sel = sel[c3["margin"][sel] >= MARGIN]
+    uv, tgt = c3["uv"][sel], c3["tgt"][sel]
+    lat_np, Ws, bs = c3["lat_np"], c3["Ws"], c3["bs"]
+    shift = c3["wl"].shift
+    gW, gb, gl, _ = _gpu_autograd(lat_np, Ws, bs, uv, tgt, shift)
+    olat = O.Latents(lat_np, shift=shift)
+    of = O.decode(olat, c3["omlp"], uv)
+    oW, ob, ol = O.backward(olat, c3["omlp"], uv, 2.0 * (of - tgt) / of.size)
+
+    def loss(Ws_, bs_, lat_):
+        ff = O.decode(O.Latents(lat_, shift=shift), O.Mlp(Ws_, bs_), uv)
+        return np.mean((ff - tgt) ** 2)
+
+    h = 1e-3
+    checked = tried = 0
+    while checked < 64 and tried < 160:
+        tried += 1
+        kind = tried % 3
+        W2 = [w.astype(np.float64) for w in Ws]
+        b2 = [b.astype(np.float64) for b in bs]
+        l2 = list(lat_np)
+        if kind == 0:
+            l = int(rng.integers(3)); idx = tuple(int(rng.integers(s)) for s in W2[l].shape)
+            arr, got, ref = W2, gW[l][idx], oW[l][idx]
+        elif kind == 1:
+            l = int(rng.integers(3)); idx = (int(rng.integers(b2[l].shape[0])),)
+            arr, got, ref = b2, gb[l][idx], ob[l][idx]
+        else:
+            l = int(rng.integers(4)); nz = np.argwhere(ol[l] != 0); idx = tuple(nz[rng.integers(len(nz))])
+            l2 = [a.astype(np.float64) for a in lat_np]
+            arr, got, ref = l2, gl[l][idx], ol[l][idx]
+        base = arr[l][idx]
+        arr[l][idx] = base + h
+        lp = loss(W2, b2, l2)
+        arr[l][idx] = base - h
+        lm = loss(W2, b2, l2)
+        arr[l][idx] = base
+        fd = (lp - lm) / (2 * h)
+        # a +-h step across a ReLU kink of some sample breaks the central
+        # difference; such parameters show up as the FD disagreeing with the
+        # FP64 analytic gradient and are skipped
+        if abs(fd - ref) > 1e-4 * max(abs(ref), 1e-7) + 1e-10:
+            continue
+        assert abs(got - fd) <= 1e-3 * max(abs(fd), 1e-7) + 1e-10, (kind, l, idx, got, fd)
+        checked += 1
+    print(f"[fd] {checked} parameters checked in {tried} tries", flush=True)
+    assert checked >= 64
+
+
+def test_backward_empty_batch_gives_zero():
+    ntc = _ntc()
+    rng = np.random.default_rng(2)
+    lat = ntc.Latents(I.f32_pyramid(rng, [(16, 16), (8, 8), (8, 8), (4, 4)]))
+    Ws, bs = I.xavier_mlp(rng, (14, 32, 32, 8), bias="normal")
+    mlp = ntc.Mlp(Ws, bs)
+    gW, gb, gl = ntc.decode_backward(lat, mlp, torch.zeros((0, 2), device="cuda"),
+                                     torch.zeros((0, 8), device="cuda"))
+    torch.cuda.synchronize()
+    assert all(float(t.abs().max()) == 0.0 for t in gW + gb + gl)

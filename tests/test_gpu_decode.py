@@ -1,0 +1,234 @@
+"""GPU parity of the fused decode against the FP64 oracle.
+
+Gates: BC1 texel decode bit-exact; outputs within 1e-5 relative (FP32),
+2e-3 absolute (FP16) and 3e-2 absolute (FP8 E4M3) of the exact FP64 result.
+Full-size workloads (4096^2 pixels) are checked on sampled pixels, computed
+one by one by the oracle; small workloads on every pixel.
+"""
+import numpy as np
+import pytest
+import torch
+
+import ntc_inputs as I
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32_REL = 1e-5
+TOL_F16_ABS = 2e-3
+TOL_FP8_ABS = 3e-2
+
+
+def _ntc():
+    import paper_2506_06040_amd as ntc
+    return ntc
+
+
+def _report(name, got, ref):
+    err = np.abs(got.astype(np.float64) - ref)
+    mx = err.max(axis=0)
+    rms = np.sqrt((err ** 2).mean(axis=0))
+    print(f"\n[{name}] n={got.shape[0]} per-channel max {np.array2string(mx, precision=2)} "
+          f"rms {np.array2string(rms, precision=2)}", flush=True)
+    return err
+
+
+def _gpu_case(lat_np, Ws, bs, shift, address="clamp"):
+    ntc = _ntc()
+    lat = ntc.Latents(lat_np, shift=shift, address=address)
+    mlp = ntc.Mlp(Ws, bs)
+    return lat, mlp
+
+
+def _oracle_case(lat_np, Ws, bs, shift, address="clamp"):
+    return O.Latents(lat_np, shift=shift, address=O.CLAMP if address == "clamp" else O.WRAP), O.Mlp(Ws, bs)
+
+
+def _sample_index(n, k, seed):
+    rng = np.random.default_rng(seed)
+    idx = np.concatenate([np.arange(min(n, 256)), np.arange(max(0, n - 256), n), rng.integers(0, n, k)])
+    return np.unique(idx)
+
+
+# ---------------------------------------------------------------------------
+def test_bc1_texels_bitexact():
+    ntc = _ntc()
+    for wl in (I.WORKLOADS["c1"], I.WORKLOADS["c2"]):
+        print(f"[texels] {wl.name}", flush=True)
+        lat_np = I.bc1_pyramid(I.streams(wl.seed)[0], wl.latent_sizes)
+        lat = ntc.Latents(lat_np)
+        for k in range(len(lat_np)):
+            val, num = ntc.bc1_decode_texels(lat, k)
+            val = val.cpu().numpy()
+            num = num.cpu().numpy().astype(np.int64)
+            onum, oden, oval = O.bc1_level(lat_np[k])
+            den6 = np.array([186, 378, 186], np.int64)
+            # num / den6 == onum / oden exactly
+            assert np.array_equal(num * oden.astype(np.int64), onum.astype(np.int64) * den6), (wl.name, k)
+            assert np.array_equal(val, oval.astype(np.float32)), (wl.name, k)
+
+
+def test_plain_f32_c1_all_pixels():
+    ntc = _ntc()
+    wl = I.WORKLOADS["c1"]
+    lat_np, Ws, bs, uv = I.make_workload(wl)
+    lat, mlp = _gpu_case(lat_np, Ws, bs, wl.shift)
+    out = ntc.decode(lat, mlp, torch.from_numpy(uv).cuda(), compute="f32").cpu().numpy()
+    olat, omlp = _oracle_case(lat_np, Ws, bs, wl.shift)
+    ref = O.decode(olat, omlp, uv)
+    err = _report("c1 f32", out, ref)
+    assert np.all(err <= TOL_F32_REL * np.abs(ref))
+
+
+@pytest.mark.parametrize("compute,tol", [("f16", TOL_F16_ABS), ("f32", None)])
+def test_c1_shape_variants(compute, tol):
+    """Random biases, ragged sizes, wrap addressing, no shift, uv outside [0,1],
+    fewer levels, 9 output channels."""
+    ntc = _ntc()
+    rng = np.random.default_rng(21)
+    cases = [
+        dict(n=1000, levels=4, address="clamp", shift=I.PAPER_SHIFT, dims=(14, 32, 32, 8), uvr=(0, 1)),
+        dict(n=777, levels=4, address="wrap", shift=I.PAPER_SHIFT, dims=(14, 32, 32, 8), uvr=(-0.3, 1.4)),
+        dict(n=65, levels=4, address="clamp", shift=I.NO_SHIFT, dims=(14, 64, 64, 64, 8), uvr=(-0.1, 1.1)),
+        dict(n=1, levels=4, address="clamp", shift=I.PAPER_SHIFT, dims=(14, 16, 9), uvr=(0, 1)),
+        dict(n=300, levels=2, address="clamp", shift=I.PAPER_SHIFT, dims=(8, 16, 16, 16, 16, 4), uvr=(0, 1)),
+        dict(n=500, levels=3, address="clamp", shift=I.PAPER_SHIFT, dims=(11, 32, 9), uvr=(0, 1)),
+        dict(n=129, levels=4, address="clamp", shift=I.PAPER_SHIFT, dims=(14, 64, 16), uvr=(0, 1)),
+    ]
+    for ci, c in enumerate(cases):
+        sizes = [(64, 32), (32, 32), (16, 8), (8, 8)][:c["levels"]]
+        lat_np = I.bc1_pyramid(rng, sizes)
+        Ws, bs = I.xavier_mlp(rng, c["dims"], bias="normal")
+        uv = (rng.random((c["n"], 2)) * (c["uvr"][1] - c["uvr"][0]) + c["uvr"][0]).astype(np.float32)
+        lat, mlp = _gpu_case(lat_np, Ws, bs, c["shift"], c["address"])
+        out = ntc.decode(lat, mlp, torch.from_numpy(uv).cuda(), compute=compute).cpu().numpy()
+        olat, omlp = _oracle_case(lat_np, Ws, bs, c["shift"], c["address"])
+        ref = O.decode(olat, omlp, uv)
+        err = _report(f"variant {ci} {compute}", out, ref)
+        if compute == "f32":
+            assert np.all(err <= TOL_F32_REL * np.abs(ref)), ci
+        else:
+            assert np.all(err <= tol), ci
+
+
+def test_f16_c1_all_pixels_and_emulation():
+    ntc = _ntc()
+    wl = I.WORKLOADS["c1"]
+    lat_np, Ws, bs, uv = I.make_workload(wl, bias="normal")
+    lat, mlp = _gpu_case(lat_np, Ws, bs, wl.shift)
+    out = ntc.decode(lat, mlp, torch.from_numpy(uv).cuda(), compute="f16").cpu().numpy()
+    olat, omlp = _oracle_case(lat_np, Ws, bs, wl.shift)
+    ref = O.decode(olat, omlp, uv)
+    err = _report("c1 f16", out, ref)
+    assert np.all(err <= TOL_F16_ABS)
+    # diagnostic bound: the oracle with the same binary16 rounding of
+    # inputs/weights/activations differs only by accumulation order and the
+    # FP32 feature path
+    emu = O.decode(olat, O.Mlp(Ws, bs, precision=O.FP16), uv)
+    assert np.max(np.abs(out - emu)) <= 2e-4
+
+
+def test_staged_equals_direct_and_deterministic():
+    ntc = _ntc()
+    wl = I.WORKLOADS["c1"]
+    lat_np, Ws, bs, uv = I.make_workload(wl, bias="normal")
+    lat, mlp = _gpu_case(lat_np, Ws, bs, wl.shift)
+    uvt = torch.from_numpy(uv).cuda()
+    for compute in ("f16",):
+        packed = ntc.pack(mlp, compute)
+        a = ntc.decode(lat, mlp, uvt, compute=compute, packed=packed)
+        b = ntc.decode(lat, mlp, uvt, compute=compute, packed=packed)
+        c = ntc.decode(lat, mlp, uvt, compute=compute, packed=packed, cfg=ntc.tile_cfg(stage_capacity=64))
+        d = ntc.decode(lat, mlp, uvt, compute=compute, packed=packed, cfg=ntc.tile_cfg(waves_per_cu=3))
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        assert torch.equal(a, c)
+        assert torch.equal(a, d)
+
+
+def test_random_uv_fallback_parity():
+    """Random uv: tile footprints exceed the staging capacity -> direct fetches."""
+    ntc = _ntc()
+    wl = I.WORKLOADS["c2"]
+    s_lat, s_mlp, _, _ = I.streams(wl.seed)
+    lat_np = I.bc1_pyramid(s_lat, wl.latent_sizes)
+    Ws, bs = I.xavier_mlp(s_mlp, wl.dims, bias="normal")
+    uv = I.random_uv(np.random.default_rng(5), 20000)
+    lat, mlp = _gpu_case(lat_np, Ws, bs, wl.shift)
+    out = ntc.decode(lat, mlp, torch.from_numpy(uv).cuda(), compute="f16").cpu().numpy()
+    olat, omlp = _oracle_case(lat_np, Ws, bs, wl.shift)
+    ref = O.decode(olat, omlp, uv)
+    err = _report("random uv f16", out, ref)
+    assert np.all(err <= TOL_F16_ABS)
+
+
+def test_empty_and_out_f16():
+    ntc = _ntc()
+    rng = np.random.default_rng(3)
+    lat_np = I.bc1_pyramid(rng, [(32, 32), (16, 16), (8, 8), (4, 4)])
+    Ws, bs = I.xavier_mlp(rng, (14, 32, 32, 8), bias="normal")
+    lat, mlp = _gpu_case(lat_np, Ws, bs, I.PAPER_SHIFT)
+    empty = ntc.decode(lat, mlp, torch.zeros((0, 2), device="cuda"), compute="f16")
+    assert empty.shape == (0, 8)
+    uv = rng.random((333, 2)).astype(np.float32)
+    o16 = ntc.decode(lat, mlp, torch.from_numpy(uv).cuda(), compute="f16", out_dtype=torch.float16)
+    o32 = ntc.decode(lat, mlp, torch.from_numpy(uv).cuda(), compute="f16", out_dtype=torch.float32)
+    assert o16.dtype == torch.float16
+    assert torch.equal(o16, o32.to(torch.float16))
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads (4096^2 pixels), sampled parity
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c2_case():
+    wl = I.WORKLOADS["c2"]
+    lat_np, Ws, bs, uv = I.make_workload(wl)
+    ntc = _ntc()
+    lat, mlp = _gpu_case(lat_np, Ws, bs, wl.shift)
+    uvt = torch.from_numpy(uv).cuda()
+    olat, omlp = _oracle_case(lat_np, Ws, bs, wl.shift)
+    idx = _sample_index(uv.shape[0], 30000, 7)
+    ref = O.decode_index(olat, omlp, uv, idx)
+    return dict(wl=wl, lat_np=lat_np, Ws=Ws, bs=bs, uv=uv, lat=lat, mlp=mlp, uvt=uvt, olat=olat, omlp=omlp,
+                idx=idx, ref=ref)
+
+
+def test_c2_f16_full_size_sampled(c2_case):
+    ntc = _ntc()
+    c = c2_case
+    out = ntc.decode(c["lat"], c["mlp"], c["uvt"], compute="f16")
+    got = out[torch.from_numpy(c["idx"]).cuda()].cpu().numpy()
+    err = _report("c2 f16 4096^2", got, c["ref"])
+    assert np.all(err <= TOL_F16_ABS)
+    assert torch.isfinite(out).all()
+
+
+def test_c2_f32_full_size_sampled(c2_case):
+    ntc = _ntc()
+    c = c2_case
+    out = ntc.decode(c["lat"], c["mlp"], c["uvt"], compute="f32")
+    got = out[torch.from_numpy(c["idx"]).cuda()].cpu().numpy()
+    err = _report("c2 f32 4096^2", got, c["ref"])
+    assert np.all(err <= TOL_F32_REL * np.abs(c["ref"]))
+
+
+def test_c4_fp8_full_size_sampled(c2_case):
+    ntc = _ntc()
+    c = c2_case
+    cal = torch.from_numpy(I.calibration_uv()).cuda()
+    amax = ntc.calibrate_fp8(c["lat"], c["mlp"], cal)
+    # the calibration is checked against the oracle's own ranges
+    oam = O.layer_amax(c["olat"], c["omlp"], I.calibration_uv())
+    assert np.allclose(amax.cpu().numpy(), oam, rtol=1e-5)
+    packed = ntc.pack(c["mlp"], "fp8", act_amax=amax)
+    out = ntc.decode(c["lat"], c["mlp"], c["uvt"], compute="fp8", packed=packed)
+    got = out[torch.from_numpy(c["idx"]).cuda()].cpu().numpy()
+    err = _report("c4 fp8 4096^2", got, c["ref"])
+    assert np.all(err <= TOL_FP8_ABS)
+    # diagnostic: the oracle with the same E4M3 rounding and scales
+    ws, as_ = O.fp8_scales(c["Ws"], oam)
+    emu = O.decode_index(c["olat"], O.Mlp(c["Ws"], c["bs"], precision=O.FP8, w_scale=ws, a_scale=as_), c["uv"],
+                         c["idx"])
+    d = np.abs(got - emu)
+    print(f"[c4 fp8 vs emulation] max {d.max():.3g} rms {np.sqrt((d**2).mean()):.3g}", flush=True)

@@ -144,3 +144,18 @@ def test_latent_gradient_structure(oracle_lib):
         nz = np.argwhere(np.any(glat[k] != 0, axis=2))
         assert len(nz) <= 4
         assert np.allclose(glat[k].sum(axis=(0, 1)), dx[3 * k:3 * k + 3], rtol=1e-12, atol=1e-14)
+
+
+def test_relu_margin(oracle_lib):
+    """The margin is the smallest |z| of the hidden layers, checked against
+    pre-activations built from the oracle's features and numpy matmul."""
+    O = oracle_lib
+    dims = (14, 16, 12, 8)
+    lat, Ws, bs, uv, _ = _setup(seed=17, n=200, dims=dims)
+    olat = O.Latents(lat, shift=I.PAPER_SHIFT)
+    mg = O.relu_margin(olat, O.Mlp(Ws, bs), uv)
+    x = O.features(olat, uv)
+    z1 = x @ Ws[0].T + bs[0]
+    z2 = np.maximum(z1, 0) @ Ws[1].T + bs[1]
+    ref = np.minimum(np.abs(z1).min(1), np.abs(z2).min(1))
+    assert np.allclose(mg, ref, rtol=1e-12, atol=1e-15)
