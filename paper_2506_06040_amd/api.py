@@ -160,10 +160,10 @@ def calibrate_fp8(lat: Latents, mlp: Mlp, uv: torch.Tensor, packed_f32: Optional
     return amax
 
 
-def tile_cfg(waves_per_cu: int = 0, stage_capacity: int = 0) -> A.ntc_tile_cfg:
+def tile_cfg(waves_per_cu: int = 0, stage_capacity: int = 0, tiles_per_iter: int = 0) -> A.ntc_tile_cfg:
     c = A.ntc_tile_cfg()
     c.waves_per_cu = waves_per_cu
-    c.tiles_per_iter = 0
+    c.tiles_per_iter = tiles_per_iter
     c.stage_capacity = stage_capacity
     c.reserved = 0
     return c

@@ -21,6 +21,8 @@ FLAGS = [
     "-fno-gpu-rdc",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in arch VGPRs: the epilogues read them directly
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall",
     "-Wno-unused-function",
     "-Wno-unused-variable",

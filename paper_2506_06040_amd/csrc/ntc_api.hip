@@ -237,12 +237,13 @@ ntc_status ntc_decode(const ntc_latents *lat, const ntc_mlp *mlp, int32_t comput
   if (!aligned(packed, 256)) return fail(NTC_E_ALIGN, "packed must be 256-byte aligned");
   if (!aligned(uv, 8)) return fail(NTC_E_ALIGN, "uv must be 8-byte aligned");
   if (!aligned(out, 16)) return fail(NTC_E_ALIGN, "out must be 16-byte aligned");
-  int stage_cap = 1024, waves_per_cu = 8;
+  int stage_cap = 1024, waves_per_cu = 8, tiles_per_iter = 2;
   if (cfg) {
     if (cfg->waves_per_cu) waves_per_cu = cfg->waves_per_cu;
     if (cfg->stage_capacity) stage_cap = cfg->stage_capacity;
-    if (cfg->tiles_per_iter != 0 && cfg->tiles_per_iter != 1)
-      return fail(NTC_E_UNSUPPORTED, "tiles_per_iter %d", cfg->tiles_per_iter);
+    if (cfg->tiles_per_iter) tiles_per_iter = cfg->tiles_per_iter;
+    if (tiles_per_iter != 1 && tiles_per_iter != 2)
+      return fail(NTC_E_UNSUPPORTED, "tiles_per_iter %d (1 or 2)", tiles_per_iter);
   }
   if (waves_per_cu < 1 || waves_per_cu > 32) return fail(NTC_E_SHAPE, "waves_per_cu %d outside 1..32", waves_per_cu);
   if (stage_cap < 64 || stage_cap > 4096) return fail(NTC_E_SHAPE, "stage_capacity %d outside 64..4096", stage_cap);
@@ -266,7 +267,7 @@ ntc_status ntc_decode(const ntc_latents *lat, const ntc_mlp *mlp, int32_t comput
   if (compute == NTC_F32)
     e = launch_decode_plain(a, s, nullptr, cus, (hipStream_t)stream);
   else
-    e = launch_decode_mfma(a, s, compute, cus * waves_per_cu, (hipStream_t)stream);
+    e = launch_decode_mfma(a, s, compute, tiles_per_iter, cus * waves_per_cu, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "decode launch");
   return ok();
 }

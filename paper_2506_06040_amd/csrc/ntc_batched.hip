@@ -24,22 +24,25 @@ namespace ntc {
 
 template <int HID, int NL>
 __device__ __forceinline__ void run_material(const BatchMaterial &M, const BatchItem *items, int it0, int it1,
-                                             uint32_t *stage) {
+                                             f32x4 *stage) {
   const DecodeArgs &a = M.a;
   const int lane = threadIdx.x;
   const int g = lane >> 4;
   MfmaWeights<PrecF16, HID, NL> W;
   W.load(a.packed, a.lay, lane);
+  const __amdgpu_buffer_rsrc_t wrs = make_rsrc(a.packed, (uint32_t)a.lay.total);
   const bool has_level = g < a.lat.n_levels;
-  const LevelArgs L = select_level(a.lat, g);
+  const LaneLevel L = lane_level(a.lat, g);
   for (int it = it0; it < it1; ++it) {
     const int64_t t0 = items[it].first_tile, t1 = t0 + items[it].n_tiles;
-    for (int64_t tile = t0; tile < t1; ++tile) decode_tile<PrecF16, HID, NL>(a, L, has_level, tile, stage, W);
+    const int64_t end_px = t1 * 64 < a.n ? t1 * 64 : a.n;
+    for (int64_t tile = t0; tile < t1; tile += 2)
+      decode_tiles<PrecF16, HID, NL, 2>(a, L, has_level, tile, end_px, stage, W, wrs);
   }
 }
 
 __global__ __launch_bounds__(64) void decode_batched_kernel(const uint8_t *__restrict__ plan) {
-  extern __shared__ uint32_t stage[];
+  extern __shared__ f32x4 stage[];
   const BatchPlanHeader *h = reinterpret_cast<const BatchPlanHeader *>(plan);
   const BatchMaterial *mats = reinterpret_cast<const BatchMaterial *>(plan + h->mats_off);
   const BatchItem *items = reinterpret_cast<const BatchItem *>(plan + h->items_off);
@@ -184,7 +187,7 @@ void build_plan(const BatchMaterial *mats, int n_mats, int item_tiles, int n_wav
 
 hipError_t launch_decode_batched(const uint8_t *plan_dev, const BatchPlanHeader &h, hipStream_t st) {
   if (h.n_waves < 1) return hipSuccess;
-  const size_t lds = (size_t)h.stage_cap * 4;
+  const size_t lds = (size_t)h.stage_cap * sizeof(f32x4);
   hipLaunchKernelGGL(decode_batched_kernel, dim3(h.n_waves), dim3(64), lds, st, plan_dev);
   return hipGetLastError();
 }

@@ -31,56 +31,66 @@
 
 namespace ntc {
 
-template <class P, int HID, int NL>
+template <class P, int HID, int NL, int TP>
 __global__ __launch_bounds__(64) void decode_mfma_kernel(DecodeArgs a) {
-  extern __shared__ uint32_t stage[];
+  extern __shared__ f32x4 stage[];
   const int lane = threadIdx.x;
   const int g = lane >> 4;
 
   MfmaWeights<P, HID, NL> W;
   W.load(a.packed, a.lay, lane);
+  const __amdgpu_buffer_rsrc_t wrs = make_rsrc(a.packed, (uint32_t)a.lay.total);
   const bool has_level = g < a.lat.n_levels;
-  const LevelArgs L = select_level(a.lat, g);
+  const LaneLevel L = lane_level(a.lat, g);
 
   // XCD-aware numbering: consecutive workgroups land on different XCDs;
   // renumber so that each XCD walks a contiguous range of tiles at a time.
   const int nb = gridDim.x;
   int vb = blockIdx.x;
   if ((nb & 7) == 0) vb = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-  for (int64_t tile = vb; tile < a.n_tiles; tile += nb) decode_tile<P, HID, NL>(a, L, has_level, tile, stage, W);
+  const int64_t n_iter = (a.n_tiles + TP - 1) / TP;
+  for (int64_t it = vb; it < n_iter; it += nb)
+    decode_tiles<P, HID, NL, TP>(a, L, has_level, it * TP, a.n, stage, W, wrs);
 }
 
-template <class P, int HID>
-static hipError_t launch_mfma_hid(const DecodeArgs &a, int n_layers, int grid, hipStream_t st) {
-  const size_t lds = (size_t)a.stage_cap * 4;
+template <class P, int HID, int TP>
+static hipError_t launch_mfma_tp(const DecodeArgs &a, int n_layers, int grid, hipStream_t st) {
+  const size_t lds = (size_t)a.stage_cap * sizeof(f32x4);
   switch (n_layers) {
-    case 2: hipLaunchKernelGGL((decode_mfma_kernel<P, HID, 2>), dim3(grid), dim3(64), lds, st, a); break;
-    case 3: hipLaunchKernelGGL((decode_mfma_kernel<P, HID, 3>), dim3(grid), dim3(64), lds, st, a); break;
-    case 4: hipLaunchKernelGGL((decode_mfma_kernel<P, HID, 4>), dim3(grid), dim3(64), lds, st, a); break;
-    case 5: hipLaunchKernelGGL((decode_mfma_kernel<P, HID, 5>), dim3(grid), dim3(64), lds, st, a); break;
+    case 2: hipLaunchKernelGGL((decode_mfma_kernel<P, HID, 2, TP>), dim3(grid), dim3(64), lds, st, a); break;
+    case 3: hipLaunchKernelGGL((decode_mfma_kernel<P, HID, 3, TP>), dim3(grid), dim3(64), lds, st, a); break;
+    case 4: hipLaunchKernelGGL((decode_mfma_kernel<P, HID, 4, TP>), dim3(grid), dim3(64), lds, st, a); break;
+    case 5: hipLaunchKernelGGL((decode_mfma_kernel<P, HID, 5, TP>), dim3(grid), dim3(64), lds, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+template <class P, int HID>
+static hipError_t launch_mfma_hid(const DecodeArgs &a, int n_layers, int tp, int grid, hipStream_t st) {
+  return tp == 2 ? launch_mfma_tp<P, HID, 2>(a, n_layers, grid, st) : launch_mfma_tp<P, HID, 1>(a, n_layers, grid, st);
+}
+
 template <class P>
-static hipError_t launch_mfma_prec(const DecodeArgs &a, const MlpShape &s, int grid, hipStream_t st) {
+static hipError_t launch_mfma_prec(const DecodeArgs &a, const MlpShape &s, int tp, int grid, hipStream_t st) {
   switch (s.hid) {
-    case 16: return launch_mfma_hid<P, 16>(a, s.n_layers, grid, st);
-    case 32: return launch_mfma_hid<P, 32>(a, s.n_layers, grid, st);
-    case 64: return launch_mfma_hid<P, 64>(a, s.n_layers, grid, st);
+    case 16: return launch_mfma_hid<P, 16>(a, s.n_layers, tp, grid, st);
+    case 32: return launch_mfma_hid<P, 32>(a, s.n_layers, tp, grid, st);
+    case 64: return launch_mfma_hid<P, 64>(a, s.n_layers, tp, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_decode_mfma(const DecodeArgs &a, const MlpShape &s, int compute, int grid_waves,
-                              hipStream_t st) {
+hipError_t launch_decode_mfma(const DecodeArgs &a, const MlpShape &s, int compute, int tiles_per_iter,
+                              int grid_waves, hipStream_t st) {
+  const int tp = tiles_per_iter == 2 ? 2 : 1;
   int64_t grid = grid_waves;
-  if (grid > a.n_tiles) grid = a.n_tiles;
+  const int64_t n_iter = (a.n_tiles + tp - 1) / tp;
+  if (grid > n_iter) grid = n_iter;
   if (grid >= 8) grid &= ~(int64_t)7;
   if (grid < 1) grid = 1;
-  if (compute == 1) return launch_mfma_prec<PrecF16>(a, s, (int)grid, st);
-  if (compute == 3) return launch_mfma_prec<PrecF8>(a, s, (int)grid, st);
+  if (compute == 1) return launch_mfma_prec<PrecF16>(a, s, tp, (int)grid, st);
+  if (compute == 3) return launch_mfma_prec<PrecF8>(a, s, tp, (int)grid, st);
   return hipErrorInvalidValue;
 }
 

@@ -140,10 +140,14 @@ def test_staged_equals_direct_and_deterministic():
         b = ntc.decode(lat, mlp, uvt, compute=compute, packed=packed)
         c = ntc.decode(lat, mlp, uvt, compute=compute, packed=packed, cfg=ntc.tile_cfg(stage_capacity=64))
         d = ntc.decode(lat, mlp, uvt, compute=compute, packed=packed, cfg=ntc.tile_cfg(waves_per_cu=3))
+        e = ntc.decode(lat, mlp, uvt, compute=compute, packed=packed, cfg=ntc.tile_cfg(tiles_per_iter=1))
+        f = ntc.decode(lat, mlp, uvt[:4099], compute=compute, packed=packed, cfg=ntc.tile_cfg(tiles_per_iter=2))
         torch.cuda.synchronize()
         assert torch.equal(a, b)
         assert torch.equal(a, c)
         assert torch.equal(a, d)
+        assert torch.equal(a, e)
+        assert torch.equal(a[:4099], f)
 
 
 def test_random_uv_fallback_parity():
