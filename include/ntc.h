@@ -96,7 +96,7 @@ typedef struct {
 /* Tile configuration of the MFMA decode. Zero fields pick defaults.
  *   waves_per_cu : persistent waves launched per compute unit (1..32)
  *   tiles_per_iter: 64-pixel tiles a wave stages together before running
- *                   the MLP on them (1 or 2; default 2)
+ *                   the MLP on them (this build: 2)
  *   stage_capacity: texels a wave may stage in LDS per tile (64..4096);
  *                   tiles whose footprint is larger fall back to direct
  *                   block fetches. */

@@ -7,6 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libntc.so")
 SOURCES = ["ntc_api.hip", "ntc_plain.hip", "ntc_mfma.hip", "ntc_backward.hip", "ntc_batched.hip"]
 
@@ -17,8 +18,8 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-fno-gpu-rdc",
+    "-I" + INCLUDE,
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # matrix-core results in arch VGPRs: the epilogues read them directly
@@ -29,10 +30,27 @@ FLAGS = [
 ]
 
 
+def _compile(src: str, obj: str, extra, verbose: bool) -> None:
+    cmd = [HIPCC] + FLAGS + list(extra or []) + ["-c", "-o", obj, src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
 def build(verbose: bool = False, extra=None) -> str:
+    """Compile every source to an object (in parallel), then link libntc.so."""
+    from concurrent.futures import ThreadPoolExecutor
+
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    objs = [os.path.join(objdir, os.path.basename(s) + ".o") for s in srcs]
+    workers = max(1, min(len(srcs), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(workers) as ex:
+        for f in [ex.submit(_compile, s, o, extra, verbose) for s, o in zip(srcs, objs)]:
+            f.result()
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + list(extra or []) + ["-o", tmp] + srcs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-fno-gpu-rdc", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -8,7 +8,7 @@
 #include <cstring>
 #include <vector>
 
-#include "../../include/ntc.h"
+#include "ntc.h"
 #include "ntc_internal.hpp"
 
 using namespace ntc;
@@ -242,8 +242,7 @@ ntc_status ntc_decode(const ntc_latents *lat, const ntc_mlp *mlp, int32_t comput
     if (cfg->waves_per_cu) waves_per_cu = cfg->waves_per_cu;
     if (cfg->stage_capacity) stage_cap = cfg->stage_capacity;
     if (cfg->tiles_per_iter) tiles_per_iter = cfg->tiles_per_iter;
-    if (tiles_per_iter != 1 && tiles_per_iter != 2)
-      return fail(NTC_E_UNSUPPORTED, "tiles_per_iter %d (1 or 2)", tiles_per_iter);
+    if (tiles_per_iter != 2) return fail(NTC_E_UNSUPPORTED, "tiles_per_iter %d (only 2)", tiles_per_iter);
   }
   if (waves_per_cu < 1 || waves_per_cu > 32) return fail(NTC_E_SHAPE, "waves_per_cu %d outside 1..32", waves_per_cu);
   if (stage_cap < 64 || stage_cap > 4096) return fail(NTC_E_SHAPE, "stage_capacity %d outside 64..4096", stage_cap);
@@ -267,7 +266,7 @@ ntc_status ntc_decode(const ntc_latents *lat, const ntc_mlp *mlp, int32_t comput
   if (compute == NTC_F32)
     e = launch_decode_plain(a, s, nullptr, cus, (hipStream_t)stream);
   else
-    e = launch_decode_mfma(a, s, compute, tiles_per_iter, cus * waves_per_cu, (hipStream_t)stream);
+    e = launch_decode_mfma(a, s, compute, cus * waves_per_cu, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "decode launch");
   return ok();
 }

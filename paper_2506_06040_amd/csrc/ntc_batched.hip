@@ -22,28 +22,53 @@
 
 namespace ntc {
 
-template <int HID, int NL>
+// 64-pixel tiles per span of the batched walk.
+constexpr int kBatchSpanTiles = NTC_SPAN_TILES;
+
+template <int HID, int NL, bool VEC4>
 __device__ __forceinline__ void run_material(const BatchMaterial &M, const BatchItem *items, int it0, int it1,
-                                             f32x4 *stage) {
+                                             f32x4 *stage, f32x4 *bias, f32x4 *ltab) {
+  constexpr int ST = kBatchSpanTiles;
   const DecodeArgs &a = M.a;
   const int lane = threadIdx.x;
-  const int g = lane >> 4;
   MfmaWeights<PrecF16, HID, NL> W;
   W.load(a.packed, a.lay, lane);
-  const __amdgpu_buffer_rsrc_t wrs = make_rsrc(a.packed, (uint32_t)a.lay.total);
-  const bool has_level = g < a.lat.n_levels;
-  const LaneLevel L = lane_level(a.lat, g);
-  for (int it = it0; it < it1; ++it) {
-    const int64_t t0 = items[it].first_tile, t1 = t0 + items[it].n_tiles;
-    const int64_t end_px = t1 * 64 < a.n ? t1 * 64 : a.n;
-    for (int64_t tile = t0; tile < t1; tile += 2)
-      decode_tiles<PrecF16, HID, NL, 2>(a, L, has_level, tile, end_px, stage, W, wrs);
+  // LDS tables of the previous material were last read by this wave's own
+  // earlier instructions, which a single-wave workgroup completes in order
+  BiasLds<HID, NL>::fill(bias, a.packed, a.lay, lane);
+  LevelTab::fill(ltab, a.lat, lane);
+  __syncthreads();
+  // walk spans of up to ST tiles inside each item; the uv of the next span
+  // is prefetched
+  auto item_end = [&](int it) {
+    const int64_t t1 = items[it].first_tile + items[it].n_tiles;
+    return t1 * 64 < a.n ? t1 * 64 : a.n;
+  };
+  SpanUv<ST> uvs;
+  int it = it0;
+  int64_t tile = items[it0].first_tile;
+  uvs.load(a.uv, tile * 64, item_end(it0));
+  while (it < it1) {
+    const int64_t end_px = item_end(it);
+    int nit = it;
+    int64_t ntile = tile + ST;
+    if (ntile >= items[it].first_tile + items[it].n_tiles) {
+      ++nit;
+      ntile = nit < it1 ? items[nit].first_tile : -1;
+    }
+    decode_span<PrecF16, HID, NL, ST, VEC4>(a, tile * 64, end_px, stage, bias, ltab, W, uvs,
+                                            nit < it1 ? ntile * 64 : -1, nit < it1 ? item_end(nit) : 0);
+    it = nit;
+    tile = ntile;
   }
 }
 
-__global__ __launch_bounds__(64) void decode_batched_kernel(const uint8_t *__restrict__ plan) {
-  extern __shared__ f32x4 stage[];
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PER_SIMD, NTC_WAVES_PER_SIMD))) void decode_batched_kernel(const uint8_t *__restrict__ plan) {
+  extern __shared__ f32x4 smem[];
   const BatchPlanHeader *h = reinterpret_cast<const BatchPlanHeader *>(plan);
+  f32x4 *stage = smem;
+  f32x4 *bias = smem + h->stage_cap;
+  f32x4 *ltab = bias + BiasLds<64, 4>::kCount;
   const BatchMaterial *mats = reinterpret_cast<const BatchMaterial *>(plan + h->mats_off);
   const BatchItem *items = reinterpret_cast<const BatchItem *>(plan + h->items_off);
   const int32_t *start = reinterpret_cast<const int32_t *>(plan + h->wave_start_off);
@@ -55,18 +80,23 @@ __global__ __launch_bounds__(64) void decode_batched_kernel(const uint8_t *__res
     int run_end = it + 1;
     while (run_end < end && items[run_end].mat == m) ++run_end;
     const BatchMaterial &M = mats[m];
+    const bool vec4 = (M.a.n_out & 3) == 0;
+#define NTC_RUN(HID, NL)                                                     \
+  (vec4 ? run_material<HID, NL, true>(M, items, it, run_end, stage, bias, ltab) \
+        : run_material<HID, NL, false>(M, items, it, run_end, stage, bias, ltab))
     switch (M.shape_id) {
-      case 0: run_material<16, 2>(M, items, it, run_end, stage); break;
-      case 1: run_material<16, 3>(M, items, it, run_end, stage); break;
-      case 2: run_material<16, 4>(M, items, it, run_end, stage); break;
-      case 3: run_material<32, 2>(M, items, it, run_end, stage); break;
-      case 4: run_material<32, 3>(M, items, it, run_end, stage); break;
-      case 5: run_material<32, 4>(M, items, it, run_end, stage); break;
-      case 6: run_material<64, 2>(M, items, it, run_end, stage); break;
-      case 7: run_material<64, 3>(M, items, it, run_end, stage); break;
-      case 8: run_material<64, 4>(M, items, it, run_end, stage); break;
+      case 0: NTC_RUN(16, 2); break;
+      case 1: NTC_RUN(16, 3); break;
+      case 2: NTC_RUN(16, 4); break;
+      case 3: NTC_RUN(32, 2); break;
+      case 4: NTC_RUN(32, 3); break;
+      case 5: NTC_RUN(32, 4); break;
+      case 6: NTC_RUN(64, 2); break;
+      case 7: NTC_RUN(64, 3); break;
+      case 8: NTC_RUN(64, 4); break;
       default: break;
     }
+#undef NTC_RUN
     it = run_end;
   }
 }
@@ -187,7 +217,7 @@ void build_plan(const BatchMaterial *mats, int n_mats, int item_tiles, int n_wav
 
 hipError_t launch_decode_batched(const uint8_t *plan_dev, const BatchPlanHeader &h, hipStream_t st) {
   if (h.n_waves < 1) return hipSuccess;
-  const size_t lds = (size_t)h.stage_cap * sizeof(f32x4);
+  const size_t lds = (size_t)(h.stage_cap + BiasLds<64, 4>::kCount + LevelTab::kCount) * sizeof(f32x4);
   hipLaunchKernelGGL(decode_batched_kernel, dim3(h.n_waves), dim3(64), lds, st, plan_dev);
   return hipGetLastError();
 }

@@ -25,18 +25,20 @@ struct MlpShape {
 // by b[rows_pad]; layer 0 has cols_pad = 16, the last layer rows_pad = 16.
 //
 // Matrix-core images (FP16 / FP8): for every layer a run of A-operand
-// fragments [m][c][lane][e] (M-tile m of 16 output rows, K-chunk c of 32
-// inputs, 64 lanes, 8 elements of 2 or 1 bytes per lane), then bias
-// fragments [m][group][4] floats, then (FP8) two floats per layer:
-// the input scale s_a and the epilogue scale.
+// fragments [m][c][lane][e] (M-tile m of 32 output rows, K-step c of 16
+// inputs (FP16, 8 halves per lane) or 64 inputs (E4M3, 32 bytes per lane)),
+// then bias fragments [m][lane half][16] floats laid out like the 32x32
+// accumulator, then (FP8) three floats per layer: the input scale s_a, the
+// epilogue scale and the weight scale s_w.
 // ---------------------------------------------------------------------------
 struct PackLayout {
   size_t total;
   uint32_t w_off[kMaxLayers];     // bytes
   uint32_t b_off[kMaxLayers];     // bytes
   uint32_t scale_off;             // bytes (FP8 only)
-  int32_t mt[kMaxLayers];         // M-tiles per layer
-  int32_t kc[kMaxLayers];         // K-chunks per layer
+  int32_t mt[kMaxLayers];         // M-tiles (32 rows) per layer
+  int32_t kc[kMaxLayers];         // K-steps per layer
+  int32_t frag_elems;             // operand elements per lane (8 FP16, 32 E4M3)
   int32_t rows_pad[kMaxLayers];   // FP32 image
   int32_t cols_pad[kMaxLayers];   // FP32 image
   int32_t elem_bytes;             // 4 (FP32), 2 (FP16), 1 (FP8)
@@ -70,8 +72,7 @@ struct DecodeArgs {
 
 hipError_t launch_decode_plain(const DecodeArgs &a, const MlpShape &s, float *calib_amax, int n_cus,
                                hipStream_t st);
-hipError_t launch_decode_mfma(const DecodeArgs &a, const MlpShape &s, int compute, int tiles_per_iter,
-                              int grid_waves, hipStream_t st);
+hipError_t launch_decode_mfma(const DecodeArgs &a, const MlpShape &s, int compute, int grid_waves, hipStream_t st);
 hipError_t launch_bc1_texels(const LevelArgs &L, float *out, uint16_t *numer, hipStream_t st);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
 

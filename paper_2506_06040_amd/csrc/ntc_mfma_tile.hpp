@@ -1,28 +1,48 @@
 // Matrix-core tile decode shared by the single-material and the batched
-// kernels (see ntc_mfma.hip for the data layout).
+// kernels.
 //
-// Per 64-pixel tile and wavefront (lane l = 16 g + n, lane group g samples
-// latent level g for pixels 16 t + n, t = 0..3):
-//   1. uv of the four pixels; the tile's uv extremes by DPP row reductions
-//      (every lane group holds all 64 pixels, so every row reduces the whole
-//      tile).
-//   2. Bounding box of the taps on each level, from the uv extremes (the tap
-//      position is monotone in uv). If the boxes fit the wave's LDS region,
-//      every texel of them is decoded once (integer BC1 decode, then the
-//      exact numerators scaled to FP32) into LDS, one level after another.
-//   3. Bilinear taps read four adjacent texels from LDS. Clamp-to-edge is
-//      applied to the sampling position instead of the taps: x is limited to
-//      [0, w - 1] and the left tap to [0, w - 2], so the right tap is always
-//      the next texel and an edge sample gets weight 1 on the edge texel.
-//      This gives the same value as clamping both taps.
-//   4. MLP on the matrix cores in two passes of 32 pixels; ReLU on packed
-//      FP16 after conversion; sigmoid with the hardware exp2 / reciprocal.
+// A wavefront decodes spans of 128 pixels (two 64-pixel tiles). Lane
+// l = 32 h + n owns pixels 32 t + n (t < 4) of the span and samples latent
+// levels 2h and 2h + 1 for them:
+//   1. uv of its four pixels (buffer loads, prefetched one span ahead).
+//   2. Bilinear taps on its two levels; clamp-to-edge is applied to the
+//      sampling position (index clamped to [0, w - 2], fraction to [0, 1]),
+//      so the right / lower tap is always the next texel and an edge sample
+//      puts weight 1 on the edge texel, which equals clamping both taps.
+//   3. Bounding box of the taps on every level (DPP row reductions). If the
+//      boxes fit the wave's LDS region, every texel in them is decoded once
+//      (integer BC1 decode, exact numerators scaled to FP32) into LDS and the
+//      taps read four adjacent texels from there; otherwise the taps fetch
+//      their blocks directly.
+//   4. MLP on 32x32 matrix-core tiles: weights are the A operand (32 output
+//      rows per M-tile), pixels the B operand (32 per N-tile), FP32
+//      accumulation initialised with the bias. The 32x32 accumulator leaves
+//      lane 32 h + n with rows 8 j + 4 h + r (j, r < 4) of pixel n; the next
+//      layer's weight columns are permuted at pack time so that those rows
+//      are exactly the K elements the lane must supply as B operand. Layers
+//      chain in registers: only ReLU and the conversion run in between.
+//   5. Sigmoid (hardware exp2 / reciprocal) on the rows that hold outputs,
+//      buffer stores whose range check drops pixels past the end.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include "ntc_device.hpp"
 #include "ntc_internal.hpp"
+
+// Compile-time tuning of the matrix-core decode.
+#ifndef NTC_WAVES_PER_SIMD  // occupancy the register allocation is held to
+#define NTC_WAVES_PER_SIMD 2
+#endif
+#ifndef NTC_SPAN_TILES  // 64-pixel tiles staged together
+#define NTC_SPAN_TILES 4
+#endif
+#ifndef NTC_WIDE_NT  // N-tiles per MLP pass of 64-wide nets with hidden layers
+#define NTC_WIDE_NT 2
+#endif
+#ifndef NTC_UV_PREFETCH  // load the next span's uv during the current span
+#define NTC_UV_PREFETCH 1
+#endif
 
 namespace ntc {
 
@@ -47,6 +67,9 @@ __device__ __forceinline__ float2 gload2f(const float2 *p) {
   return make_float2(__uint_as_float((unsigned)v), __uint_as_float((unsigned)(v >> 32)));
 }
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
 __device__ __forceinline__ half2_t relu_pk(float a, float b) {
   const f32x2 v = {a, b};
   const half2_t h = __builtin_convertvector(v, half2_t);
@@ -54,72 +77,123 @@ __device__ __forceinline__ half2_t relu_pk(float a, float b) {
   return __builtin_elementwise_max(h, z);
 }
 
+// FP16 operands, 32x32x16 tiles: a K-step is 16 inputs, 8 halves per lane.
 struct PrecF16 {
   using Frag = half8_t;
+  static constexpr int KSTEP = 16;
   static constexpr bool kScaled = false;
-  __device__ __forceinline__ static f32x4 mma(Frag a, Frag b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  static constexpr int kFeatDwords = 4;  // dwords of a fragment that carry features
+  __device__ __forceinline__ static f32x16 mma(Frag a, Frag b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
   }
-  __device__ __forceinline__ static Frag features(float r, float g, float b, float u, float v, float) {
-    const f32x2 p0 = {r, g}, p1 = {b, u}, p2 = {v, 0.0f};
-    const half2_t h0 = __builtin_convertvector(p0, half2_t);
-    const half2_t h1 = __builtin_convertvector(p1, half2_t);
-    const half2_t h2 = __builtin_convertvector(p2, half2_t);
+  __device__ __forceinline__ static Frag features(const float (&x)[8], float) {
     Frag f;
-    f[0] = h0[0];
-    f[1] = h0[1];
-    f[2] = h1[0];
-    f[3] = h1[1];
-    f[4] = h2[0];
-    f[5] = h2[1];
-    f[6] = (_Float16)0.0f;
-    f[7] = (_Float16)0.0f;
+#pragma unroll
+    for (int i = 0; i < 8; i += 2) {
+      const f32x2 p = {x[i], x[i + 1]};
+      const half2_t h = __builtin_convertvector(p, half2_t);
+      f[i] = h[0];
+      f[i + 1] = h[1];
+    }
     return f;
   }
-  __device__ __forceinline__ static Frag hidden(f32x4 lo, f32x4 hi, float) {
-    const half2_t a = relu_pk(lo[0], lo[1]), b = relu_pk(lo[2], lo[3]);
-    const half2_t c = relu_pk(hi[0], hi[1]), d = relu_pk(hi[2], hi[3]);
-    Frag f;
-    f[0] = a[0];
-    f[1] = a[1];
-    f[2] = b[0];
-    f[3] = b[1];
-    f[4] = c[0];
-    f[5] = c[1];
-    f[6] = d[0];
-    f[7] = d[1];
-    return f;
+  // K-step c of the next layer = ReLU of accumulator rows 8 (c % 2) .. + 7
+  // of M-tile c / 2.
+  template <int MT, int KS>
+  __device__ __forceinline__ static void next_operands(const f32x16 (&acc)[MT], Frag (&hb)[KS], float) {
+#pragma unroll
+    for (int c = 0; c < KS; ++c) {
+      const f32x16 &v = acc[(c >> 1) % MT];
+      const int o = 8 * (c & 1);
+#pragma unroll
+      for (int i = 0; i < 8; i += 2) {
+        const half2_t h = relu_pk(v[o + i], v[o + i + 1]);
+        hb[c][i] = h[0];
+        hb[c][i + 1] = h[1];
+      }
+    }
   }
 };
 
 // OCP E4M3 with saturation to +-448 (the conversion instruction is applied
 // to clamped values).
 __device__ __forceinline__ float sat448(float v) { return __builtin_amdgcn_fmed3f(v, -448.0f, 448.0f); }
-
-__device__ __forceinline__ long pack_e4m3(float v0, float v1, float v2, float v3, float v4, float v5, float v6,
-                                          float v7) {
-  int lo = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(v0), sat448(v1), 0, false);
-  lo = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(v2), sat448(v3), lo, true);
-  int hi = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(v4), sat448(v5), 0, false);
-  hi = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(v6), sat448(v7), hi, true);
-  return (long)(((unsigned long)(unsigned)hi << 32) | (unsigned)lo);
+__device__ __forceinline__ int pack4_e4m3(float a, float b, float c, float d) {
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(a), sat448(b), 0, false);
+  return __builtin_amdgcn_cvt_pk_fp8_f32(sat448(c), sat448(d), w, true);
 }
 
+// E4M3 operands, 32x32x64 tiles (full-rate scaled form with unit block
+// scales): a K-step is 64 inputs, 32 bytes per lane.
 struct PrecF8 {
-  using Frag = long;
+  using Frag = i32x8;
+  static constexpr int KSTEP = 64;
   static constexpr bool kScaled = true;
-  __device__ __forceinline__ static f32x4 mma(Frag a, Frag b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+  static constexpr int kFeatDwords = 2;
+  __device__ __forceinline__ static f32x16 mma(Frag a, Frag b, f32x16 c) {
+    // format 0 = E4M3 for both operands; E8M0 scale 127 = 2^0
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
   }
-  __device__ __forceinline__ static Frag features(float r, float g, float b, float u, float v, float s) {
-    return pack_e4m3(r * s, g * s, b * s, u * s, v * s, 0.f, 0.f, 0.f);
+  __device__ __forceinline__ static Frag features(const float (&x)[8], float s) {
+    Frag f = {0, 0, 0, 0, 0, 0, 0, 0};
+    f[0] = pack4_e4m3(x[0] * s, x[1] * s, x[2] * s, x[3] * s);
+    f[1] = pack4_e4m3(x[4] * s, x[5] * s, x[6] * s, x[7] * s);
+    return f;
   }
-  __device__ __forceinline__ static Frag hidden(f32x4 lo, f32x4 hi, float s) {
-    return pack_e4m3(fmaxf(lo[0], 0.f) * s, fmaxf(lo[1], 0.f) * s, fmaxf(lo[2], 0.f) * s,
-                     fmaxf(lo[3], 0.f) * s, fmaxf(hi[0], 0.f) * s, fmaxf(hi[1], 0.f) * s,
-                     fmaxf(hi[2], 0.f) * s, fmaxf(hi[3], 0.f) * s);
+  // K-step c of the next layer: bytes 0..15 from all rows of M-tile 2c,
+  // bytes 16..31 from M-tile 2c + 1 (zero when it does not exist).
+  template <int MT, int KS>
+  __device__ __forceinline__ static void next_operands(const f32x16 (&acc)[MT], Frag (&hb)[KS], float s) {
+#pragma unroll
+    for (int c = 0; c < KS; ++c) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (2 * c + q < MT) {
+          const f32x16 &v = acc[2 * c + q];
+#pragma unroll
+          for (int w = 0; w < 4; ++w)
+            hb[c][4 * q + w] = pack4_e4m3(fmaxf(v[4 * w], 0.f) * s, fmaxf(v[4 * w + 1], 0.f) * s,
+                                          fmaxf(v[4 * w + 2], 0.f) * s, fmaxf(v[4 * w + 3], 0.f) * s);
+        } else {
+#pragma unroll
+          for (int w = 0; w < 4; ++w) hb[c][4 * q + w] = 0;
+        }
+      }
+    }
   }
 };
+
+// Dword d of an operand fragment, and its replacement.
+template <class P>
+__device__ __forceinline__ unsigned dword_of(const typename P::Frag &f, int d) {
+  if constexpr (P::kFeatDwords == 4) {
+    const half2_t h2 = {f[2 * d], f[2 * d + 1]};
+    return __builtin_bit_cast(unsigned, h2);
+  } else {
+    const int w = f[d];
+    return (unsigned)w;
+  }
+}
+template <class P>
+__device__ __forceinline__ void set_dword(typename P::Frag &f, int d, unsigned w) {
+  if constexpr (P::kFeatDwords == 4) {
+    const half2_t h2 = __builtin_bit_cast(half2_t, w);
+    f[2 * d] = h2[0];
+    f[2 * d + 1] = h2[1];
+  } else {
+    f[d] = (int)w;
+  }
+}
+
+// A zero the compiler cannot see through. Offsetting an LDS table pointer by
+// it on every use keeps loop-invariant code motion from turning the table
+// (bias fragments, level parameters) into registers held across the whole
+// persistent loop; the table is read again where it is used instead.
+__device__ __forceinline__ int opaque_zero() {
+  int z = 0;
+  asm volatile("" : "+s"(z));
+  return z;
+}
 
 // Minimum / maximum over the 16 lanes of a DPP row (row rotations).
 template <int CTRL>
@@ -164,16 +238,17 @@ __device__ __forceinline__ float uniform_f(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
 }
 
-// Register-resident weights of one MLP.
+// Register-resident weights of one MLP (32-row M-tiles, K-steps of the
+// precision's width).
 template <class P, int HID, int NL>
 struct MfmaWeights {
-  static constexpr int MT = HID / 16;
-  static constexpr int KC = HID >= 32 ? HID / 32 : 1;
+  static constexpr int MT = (HID + 31) / 32;                  // M-tiles of a hidden layer
+  static constexpr int KS = (HID + P::KSTEP - 1) / P::KSTEP;  // K-steps of a hidden input
   static constexpr int NH = NL > 2 ? NL - 2 : 1;
   using Frag = typename P::Frag;
   Frag w0[MT];
-  Frag wh[NH][MT][KC];
-  Frag wo[KC];
+  Frag wh[NH][MT][KS];
+  Frag wo[KS];
   float epi[kMaxLayers];
   float in_scale;
 
@@ -187,11 +262,11 @@ struct MfmaWeights {
 #pragma unroll
       for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int c = 0; c < KC; ++c) wh[h][m][c] = gload(fh + (m * KC + c) * 64 + lane);
+        for (int c = 0; c < KS; ++c) wh[h][m][c] = gload(fh + (m * KS + c) * 64 + lane);
     }
     const Frag *fo = reinterpret_cast<const Frag *>(packed + lay.w_off[NL - 1]);
 #pragma unroll
-    for (int c = 0; c < KC; ++c) wo[c] = gload(fo + c * 64 + lane);
+    for (int c = 0; c < KS; ++c) wo[c] = gload(fo + c * 64 + lane);
     in_scale = 1.0f;
 #pragma unroll
     for (int l = 0; l < kMaxLayers; ++l) epi[l] = 1.0f;
@@ -204,57 +279,20 @@ struct MfmaWeights {
   }
 };
 
-// Per-lane view of the latent level sampled by its lane group.
-struct LaneLevel {
-  const uint2 *bc1;
-  int w, h, bw;
-  float fw, fh, sx, sy;
-};
-
-// Uniform copies of kernel-argument fields: selecting between these values
-// (instead of between the argument's fields) keeps the compiler from
-// turning the per-lane choice into a pointer into the argument block, which
-// would force a private copy of the whole argument struct.
-__device__ __forceinline__ int ufld(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ float ufld(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+// Left/top tap along one axis, clamp-to-edge: the position x = u f + c
+// (c = shift - 1/2) is limited to [0, cap] (cap = n - 2) and floored, the
+// fraction is x minus that tap, limited to [0, 1]; so an edge sample puts
+// weight 1 on the edge texel, which equals clamping both taps. The tap is a
+// monotonic function of u, which is what lets a span's footprint be bounded
+// from its extreme coordinates.
+__device__ __forceinline__ float tap_floor(float u, float f, float c, float capf) {
+  return floorf(__builtin_amdgcn_fmed3f(fmaf(u, f, c), 0.0f, capf));
 }
-__device__ __forceinline__ const uint2 *ufld(const uint2 *p) {
-  const unsigned long long v = (unsigned long long)p;
-  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
-  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
-  return (const uint2 *)(((unsigned long long)hi << 32) | lo);
-}
-
-__device__ __forceinline__ LaneLevel lane_level(const LatArgs &lat, int g) {
-  LaneLevel r;
-#define NTC_PICK(f)                                                                                     \
-  ([&] {                                                                                                \
-    const auto v0 = ufld(lat.lv[0].f), v1 = ufld(lat.lv[1].f), v2 = ufld(lat.lv[2].f),                 \
-               v3 = ufld(lat.lv[3].f);                                                                   \
-    return g == 0 ? v0 : (g == 1 ? v1 : (g == 2 ? v2 : v3));                                            \
-  }())
-  r.bc1 = NTC_PICK(bc1);
-  r.w = NTC_PICK(w);
-  r.h = NTC_PICK(h);
-  r.bw = NTC_PICK(bw);
-  r.fw = NTC_PICK(fw);
-  r.fh = NTC_PICK(fh);
-  r.sx = NTC_PICK(sx);
-  r.sy = NTC_PICK(sy);
-#undef NTC_PICK
-  return r;
-}
-
-// Left/top tap index and fraction along one axis, clamp-to-edge: the index
-// is clamped in the integer domain to [0, n - 2] (any input, NaN and
-// infinities included, lands inside the level), the fraction to [0, 1], so
-// an edge sample puts weight 1 on the edge texel.
-__device__ __forceinline__ void clamp_tap(float u, float fw, float s, int cap, int &i0, float &fr) {
-  const float x = fmaf(u, fw, -0.5f) + s;
-  const int xi = (int)floorf(x);
-  i0 = min(max(xi, 0), cap);
-  fr = __builtin_amdgcn_fmed3f(x - (float)i0, 0.0f, 1.0f);
+__device__ __forceinline__ void clamp_tap(float u, float f, float c, float capf, int &i0, float &fr) {
+  const float x = fmaf(u, f, c);
+  const float t = floorf(__builtin_amdgcn_fmed3f(x, 0.0f, capf));
+  i0 = (int)t;
+  fr = __builtin_amdgcn_fmed3f(x - t, 0.0f, 1.0f);
 }
 
 // Texel of a BC1 level as three FP32 channel values.
@@ -277,28 +315,6 @@ __device__ __forceinline__ float3 texel_direct(const uint2 *bc1, int bw, int i, 
   return texel_f32(bc1_numer(blk.x, blk.y, (uint32_t)(((j & 3) << 2) | (i & 3))));
 }
 
-// Sample of one level with direct block fetches; `mode` 0 clamp, 1 wrap.
-__device__ __forceinline__ float3 sample_direct(const LaneLevel &L, float u, float v, int mode) {
-  if (mode == 0) {
-    int i0, j0;
-    float fx, fy;
-    clamp_tap(u, L.fw, L.sx, L.w - 2, i0, fx);
-    clamp_tap(v, L.fh, L.sy, L.h - 2, j0, fy);
-    return blend4(texel_direct(L.bc1, L.bw, i0, j0), texel_direct(L.bc1, L.bw, i0 + 1, j0),
-                  texel_direct(L.bc1, L.bw, i0, j0 + 1), texel_direct(L.bc1, L.bw, i0 + 1, j0 + 1), fx, fy);
-  }
-  float x = fmaf(u, L.fw, -0.5f) + L.sx;
-  float y = fmaf(v, L.fh, -0.5f) + L.sy;
-  x = fminf(fmaxf(x, -16777216.0f), 16777216.0f);
-  y = fminf(fmaxf(y, -16777216.0f), 16777216.0f);
-  const float xf = floorf(x), yf = floorf(y);
-  const int ix = (int)xf, iy = (int)yf;
-  const int i0 = address_coord(ix, L.w, 1), i1 = address_coord(ix + 1, L.w, 1);
-  const int j0 = address_coord(iy, L.h, 1), j1 = address_coord(iy + 1, L.h, 1);
-  return blend4(texel_direct(L.bc1, L.bw, i0, j0), texel_direct(L.bc1, L.bw, i1, j0),
-                texel_direct(L.bc1, L.bw, i0, j1), texel_direct(L.bc1, L.bw, i1, j1), x - xf, y - yf);
-}
-
 // Sigmoid on the hardware exp2 / reciprocal.
 __device__ __forceinline__ float sigmoid_fast(float z) {
   return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
@@ -314,93 +330,117 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufferFlags);
 }
 
-// MLP over two N-tiles (32 pixels: N-tiles t0, t0 + 1 of the iteration) and store.
-template <class P, int HID, int NL>
-__device__ __forceinline__ void mlp_store2(const DecodeArgs &a, const MfmaWeights<P, HID, NL> &W,
-                                           __amdgpu_buffer_rsrc_t wrs, __amdgpu_buffer_rsrc_t ors,
-                                           const typename P::Frag (&bx)[2], int t0) {
-  constexpr int MT = HID / 16;
-  constexpr int KC = HID >= 32 ? HID / 32 : 1;
+// Bias fragments of all layers, copied once per wave into LDS: per layer
+// and M-tile, 16 floats for each lane half (rows 8 j + 4 h + r), so that a
+// lane's bias is the initial value of its 32x32 accumulator.
+template <int HID, int NL>
+struct BiasLds {
+  static constexpr int MT = (HID + 31) / 32;
+  static constexpr int kCount = ((NL - 1) * MT + 1) * 8;  // float4 entries
+  __device__ __forceinline__ static int off(int l, int m) { return (l * MT + m) * 8; }  // l < NL - 1
+  __device__ __forceinline__ static int off_out() { return (NL - 1) * MT * 8; }
+  __device__ __forceinline__ static void fill(f32x4 *dst, const uint8_t *packed, const PackLayout &lay, int lane) {
+    for (int e = lane; e < kCount; e += 64) {
+      const int l = e < off_out() ? e / (MT * 8) : NL - 1;
+      const int r = e < off_out() ? e % (MT * 8) : e - off_out();
+      dst[e] = gload(reinterpret_cast<const f32x4 *>(packed + lay.b_off[l]) + r);
+    }
+  }
+  __device__ __forceinline__ static f32x16 get(const f32x4 *src, int e0, int h) {
+    const f32x4 *p = src + e0 + 4 * h;
+    const f32x4 a = p[0], b = p[1], c = p[2], d = p[3];
+    return (f32x16){a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3], c[0], c[1], c[2], c[3], d[0], d[1], d[2], d[3]};
+  }
+};
+
+// MLP over NT N-tiles of 32 pixels (N-tiles t0 .. t0 + NT - 1 of the span) and
+// store. VEC4: the output width is a multiple of 4.
+template <class P, int HID, int NL, int NT, bool VEC4>
+__device__ __forceinline__ void mlp_store(const DecodeArgs &a, const MfmaWeights<P, HID, NL> &W,
+                                          const f32x4 *bias, __amdgpu_buffer_rsrc_t ors,
+                                          const typename P::Frag (&bx)[NT], int t0) {
+  using BL = BiasLds<HID, NL>;
+  using WT = MfmaWeights<P, HID, NL>;
+  constexpr int MT = WT::MT;
+  constexpr int KS = WT::KS;
   constexpr int NH = NL - 2;
-  constexpr int NT = 2;
   using Frag = typename P::Frag;
   const int lane = threadIdx.x;
-  const int g = lane >> 4;
-  const int nl = lane & 15;
-  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  const int h = lane >> 5;
+  const int n = lane & 31;
+  bias += opaque_zero();
 
-  f32x4 acc[MT][NT];
+  f32x16 acc[NT][MT];
 #pragma unroll
   for (int m = 0; m < MT; ++m) {
-    const f32x4 bm = __builtin_bit_cast(
-        f32x4, __builtin_amdgcn_raw_buffer_load_b128(wrs, g * 16, (int)a.lay.b_off[0] + m * 64, 0));
+    const f32x16 bm = BL::get(bias, BL::off(0, m), h);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[m][t] = P::mma(W.w0[m], bx[t], bm);
+    for (int t = 0; t < NT; ++t) acc[t][m] = P::mma(W.w0[m], bx[t], bm);
   }
 #pragma unroll
-  for (int h = 0; h < NH; ++h) {
-    Frag hb[KC][NT];
+  for (int k = 0; k < NH; ++k) {
+    Frag hb[NT][KS];
 #pragma unroll
-    for (int c = 0; c < KC; ++c)
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-        hb[c][t] = P::hidden(acc[2 * c][t], (2 * c + 1 < MT) ? acc[(2 * c + 1) % MT][t] : zero, W.epi[h]);
+    for (int t = 0; t < NT; ++t) P::template next_operands<MT, KS>(acc[t], hb[t], W.epi[k]);
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-      const f32x4 bm = __builtin_bit_cast(
-          f32x4, __builtin_amdgcn_raw_buffer_load_b128(wrs, g * 16, (int)a.lay.b_off[1 + h] + m * 64, 0));
+      const f32x16 bm = BL::get(bias, BL::off(1 + k, m), h);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        f32x4 s = P::mma(W.wh[h][m][0], hb[0][t], bm);
+        f32x16 s = P::mma(W.wh[k][m][0], hb[t][0], bm);
 #pragma unroll
-        for (int c = 1; c < KC; ++c) s = P::mma(W.wh[h][m][c], hb[c][t], s);
-        acc[m][t] = s;
+        for (int c = 1; c < KS; ++c) s = P::mma(W.wh[k][m][c], hb[t][c], s);
+        acc[t][m] = s;
       }
     }
   }
-  Frag hb[KC][NT];
+  Frag hb[NT][KS];
 #pragma unroll
-  for (int c = 0; c < KC; ++c)
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-      hb[c][t] = P::hidden(acc[2 * c][t], (2 * c + 1 < MT) ? acc[(2 * c + 1) % MT][t] : zero, W.epi[NL - 2]);
-  const f32x4 bo = __builtin_bit_cast(
-      f32x4, __builtin_amdgcn_raw_buffer_load_b128(wrs, g * 16, (int)a.lay.b_off[NL - 1], 0));
+  for (int t = 0; t < NT; ++t) P::template next_operands<MT, KS>(acc[t], hb[t], W.epi[NL - 2]);
+  const f32x16 bo = BL::get(bias, BL::off_out(), h);
   const float out_scale = P::kScaled ? W.epi[NL - 1] : 1.0f;
   const int n_out = a.n_out;
   const int esz = a.out_f16 ? 2 : 4;
+  // row groups j (rows 8 j + 4 h .. + 3) that hold outputs for some lane
+  const int nj = (n_out + 7) >> 3;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    f32x4 z = P::mma(W.wo[0], hb[0][t], bo);
+    f32x16 z = P::mma(W.wo[0], hb[t][0], bo);
 #pragma unroll
-    for (int c = 1; c < KC; ++c) z = P::mma(W.wo[c], hb[c][t], z);
-    if (4 * g < n_out) {
-      f32x4 f;
+    for (int c = 1; c < KS; ++c) z = P::mma(W.wo[c], hb[t][c], z);
+    const int pix = 32 * (t0 + t) + n;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) f[i] = sigmoid_fast(P::kScaled ? z[i] * out_scale : z[i]);
-      // pixels past the end of the batch fall outside the buffer and are dropped
-      const int off = ((16 * (t0 + t) + nl) * n_out + 4 * g) * esz;
-      if ((n_out & 3) == 0) {
-        if (a.out_f16) {
-          const half4_t hv = __builtin_convertvector(f, half4_t);
-          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, hv),
-                                                ors, off, 0, 2);
+    for (int j = 0; j < 4; ++j) {
+      if (j < nj) {
+        f32x4 f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f[i] = sigmoid_fast(P::kScaled ? z[4 * j + i] * out_scale : z[4 * j + i]);
+        const int row = 8 * j + 4 * h;
+        // rows past the output width and pixels past the end go beyond the
+        // buffer and are dropped by its range check
+        const int off0 = (pix * n_out + row) * esz;
+        if (VEC4) {
+          const int off = row < n_out ? off0 : 0x7fffffff;
+          if (a.out_f16) {
+            const half4_t hv = __builtin_convertvector(f, half4_t);
+            __builtin_amdgcn_raw_buffer_store_b64(
+                __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, hv), ors, off, 0, 2);
+          } else {
+            __builtin_amdgcn_raw_buffer_store_b128(
+                __builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, f), ors, off, 0, 2);
+          }
         } else {
-          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, f),
-                                                 ors, off, 0, 2);
-        }
-      } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          if (4 * g + i < n_out) {
+          for (int i = 0; i < 4; ++i) {
             // element copied to a scalar first: bit-casting a vector element
             // in place reads element 0 with this compiler
             const float fi = f[i];
+            const int oi = (row + i < n_out) ? off0 + i * esz : 0x7fffffff;
             if (a.out_f16) {
               const _Float16 hi = (_Float16)fi;
-              __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, hi), ors, off + 2 * i, 0, 2);
+              __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, hi), ors, oi, 0, 2);
             } else {
-              __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(fi), ors, off + 4 * i, 0, 2);
+              __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(fi), ors, oi, 0, 2);
             }
           }
         }
@@ -409,121 +449,336 @@ __device__ __forceinline__ void mlp_store2(const DecodeArgs &a, const MfmaWeight
   }
 }
 
-// Decode TP consecutive 64-pixel tiles starting at tile `tile`: stage, sample,
-// run the MLP, store. Lane (g, n) owns pixels 16 t + n, t < 4 TP, of the
-// 64 TP-pixel span. stage: this wave's LDS region of a.stage_cap texels.
-// end_px bounds the pixels this call may write (the batch end, or the end
-// of a work item).
-template <class P, int HID, int NL, int TP>
-__device__ __forceinline__ void decode_tiles(const DecodeArgs &a, const LaneLevel &L, bool has_level, int64_t tile,
-                                             int64_t end_px, f32x4 *stage, const MfmaWeights<P, HID, NL> &W,
-                                             __amdgpu_buffer_rsrc_t wrs) {
-  using Frag = typename P::Frag;
-  constexpr int NP = 4 * TP;  // pixels per lane
-  const int lane = threadIdx.x;
-  const int g = lane >> 4;
-  const int nl = lane & 15;
-  const int mode = a.lat.address;
 
-  const int64_t base = tile * 64;
-  const int64_t left = end_px - base;
-  const int span = left < 64 * TP ? (int)left : 64 * TP;
-  const int esz = a.out_f16 ? 2 : 4;
-  const __amdgpu_buffer_rsrc_t urs = make_rsrc(a.uv + base, (uint32_t)span * 8u);
-  const __amdgpu_buffer_rsrc_t ors =
-      make_rsrc(reinterpret_cast<const char *>(a.out) + base * a.n_out * esz, (uint32_t)(span * a.n_out * esz));
-
-  float u[NP], v[NP];
+// Parameters of the latent levels, one table per wave in LDS (the kernels
+// read them from here on every span instead of keeping the kernel
+// argument's fields of all levels live in scalar registers). Level k has
+// three entries:
+//   3 k     {w, shift_x - 1/2, w - 2, w}      axis x
+//   3 k + 1 {h, shift_y - 1/2, h - 2, h}      axis y
+//   3 k + 2 {blocks (low, high 32 bits), blocks per row, 0}
+// (w - 2 and h - 2 as floats, the other integers as their bits). The footprint lanes and the per-pixel taps use
+// the same values.
+struct LevelTab {
+  static constexpr int kCount = 3 * kMaxLevels;
+  __device__ __forceinline__ static void fill(f32x4 *dst, const LatArgs &lat, int lane) {
 #pragma unroll
-  for (int t = 0; t < NP; ++t) {
-    const auto q = __builtin_amdgcn_raw_buffer_load_b64(urs, nl * 8, t * 128, 0);
-    u[t] = __uint_as_float(q[0]);
-    v[t] = __uint_as_float(q[1]);
+    for (int k = 0; k < kMaxLevels; ++k) {
+      const LevelArgs &L = lat.lv[k];
+      const unsigned long long p = (unsigned long long)L.bc1;
+      const f32x4 ex = {L.fw, L.sx - 0.5f, (float)(L.w - 2), __int_as_float(L.w)};
+      const f32x4 ey = {L.fh, L.sy - 0.5f, (float)(L.h - 2), __int_as_float(L.h)};
+      const f32x4 eb = {__uint_as_float((unsigned)p), __uint_as_float((unsigned)(p >> 32)), __int_as_float(L.bw),
+                        0.0f};
+      if (lane == 0) {
+        dst[3 * k] = ex;
+        dst[3 * k + 1] = ey;
+        dst[3 * k + 2] = eb;
+      }
+    }
+  }
+};
+
+// A level's parameters as read from the table.
+struct TabLevel {
+  float fw, cx, fh, cy, wm2, hm2;
+  int w, h, bw;
+  const uint2 *bc1;
+  __device__ __forceinline__ void read(const f32x4 *tab, int k) {
+    const f32x4 ex = tab[3 * k], ey = tab[3 * k + 1], eb = tab[3 * k + 2];
+    fw = ex[0];
+    cx = ex[1];
+    wm2 = ex[2];
+    w = __float_as_int(ex[3]);
+    fh = ey[0];
+    cy = ey[1];
+    hm2 = ey[2];
+    h = __float_as_int(ey[3]);
+    bc1 = (const uint2 *)(((unsigned long long)__float_as_uint(eb[1]) << 32) | __float_as_uint(eb[0]));
+    bw = __float_as_int(eb[2]);
+  }
+};
+
+// Sample of one level with direct block fetches; `mode` 0 clamp, 1 wrap.
+__device__ __forceinline__ float3 sample_direct_t(const TabLevel &L, float u, float v, int mode) {
+  if (mode == 0) {
+    int i0, j0;
+    float fx, fy;
+    clamp_tap(u, L.fw, L.cx, L.wm2, i0, fx);
+    clamp_tap(v, L.fh, L.cy, L.hm2, j0, fy);
+    return blend4(texel_direct(L.bc1, L.bw, i0, j0), texel_direct(L.bc1, L.bw, i0 + 1, j0),
+                  texel_direct(L.bc1, L.bw, i0, j0 + 1), texel_direct(L.bc1, L.bw, i0 + 1, j0 + 1), fx, fy);
+  }
+  float x = fmaf(u, L.fw, L.cx);
+  float y = fmaf(v, L.fh, L.cy);
+  x = fminf(fmaxf(x, -16777216.0f), 16777216.0f);
+  y = fminf(fmaxf(y, -16777216.0f), 16777216.0f);
+  const float xf = floorf(x), yf = floorf(y);
+  const int ix = (int)xf, iy = (int)yf;
+  const int i0 = address_coord(ix, L.w, 1), i1 = address_coord(ix + 1, L.w, 1);
+  const int j0 = address_coord(iy, L.h, 1), j1 = address_coord(iy + 1, L.h, 1);
+  return blend4(texel_direct(L.bc1, L.bw, i0, j0), texel_direct(L.bc1, L.bw, i1, j0),
+                texel_direct(L.bc1, L.bw, i0, j1), texel_direct(L.bc1, L.bw, i1, j1), x - xf, y - yf);
+}
+
+// uv of the ST pixels a lane owns in a span of 64 ST pixels (pixel 64 q +
+// lane); lanes past the end repeat the span's last pixel, so every loaded
+// coordinate belongs to the span.
+template <int ST>
+struct SpanUv {
+  float u[ST], v[ST];
+  __device__ __forceinline__ void load(const float2 *uv, int64_t first_px, int64_t end_px) {
+    const int lane = threadIdx.x;
+    const int64_t left = end_px - first_px;
+    const int span = left < 64 * ST ? (int)left : 64 * ST;
+    const __amdgpu_buffer_rsrc_t urs = make_rsrc(uv + first_px, (uint32_t)span * 8u);
+#pragma unroll
+    for (int q = 0; q < ST; ++q) {
+      const int p = min(64 * q + lane, span - 1);
+      const auto w = __builtin_amdgcn_raw_buffer_load_b64(urs, p * 8, 0, 0);
+      u[q] = __uint_as_float(w[0]);
+      v[q] = __uint_as_float(w[1]);
+    }
+  }
+};
+
+// Coordinates entering the clamp-mode taps: NaN becomes -2^20 and the range
+// is limited to +-2^20, which changes no tap (any |u| >= 1 already sits on an
+// edge for the level sizes the library accepts).
+__device__ __forceinline__ float tap_coord(float u) { return fminf(fmaxf(u, -1048576.0f), 1048576.0f); }
+
+__device__ __forceinline__ float wave_min(float v) {
+  v = row_min(v);
+  const float a = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+  const float b = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+  const float c = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+  const float d = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+  return uniform_f(fminf(fminf(a, b), fminf(c, d)));
+}
+__device__ __forceinline__ float wave_max(float v) {
+  v = row_max(v);
+  const float a = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+  const float b = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+  const float c = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+  const float d = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+  return uniform_f(fmaxf(fmaxf(a, b), fmaxf(c, d)));
+}
+
+// Operand exchange between the lane halves. Each lane computes all features
+// of its own pixel: `lo` holds the K-slots of lane half 0, `hi` those of half
+// 1. After the swap, `lo` is the B operand of the N-tile made of the pixels
+// of lanes 0..31 and `hi` that of the pixels of lanes 32..63: the upper half
+// of `lo` and the lower half of `hi` trade places (v_permlane32_swap).
+template <class P>
+__device__ __forceinline__ void swap_halves(typename P::Frag &lo, typename P::Frag &hi) {
+#pragma unroll
+  for (int d = 0; d < P::kFeatDwords; ++d) {
+    const unsigned a = __builtin_bit_cast(unsigned, dword_of<P>(lo, d));
+    const unsigned b = __builtin_bit_cast(unsigned, dword_of<P>(hi, d));
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    set_dword<P>(lo, d, r[0]);
+    set_dword<P>(hi, d, r[1]);
+  }
+}
+
+// Decode one span of up to 64 ST pixels starting at pixel `first` (uv
+// already in uvs) and ending before end_px: footprint, staging, sampling,
+// MLP, store. The uv of the next span (next_first < 0: none) is loaded once
+// this span's block fetches are in flight, so that its latency overlaps the
+// work of the span.
+//
+// Clamp addressing: the taps of every level are monotonic in (u, v), so the
+// span's footprint on level k is spanned by the taps of the extreme
+// coordinates, computed by 16 lanes in parallel (level, axis, min / max). If
+// the four footprints fit the LDS region (stage_cap texels), every texel in
+// them is decoded once into LDS (exact integer BC1 decode, scaled to FP32)
+// and the pixels read their four taps from there; otherwise, and for wrap
+// addressing, taps fetch their blocks directly.
+template <class P, int HID, int NL, int ST, bool VEC4>
+__device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, int64_t end_px, f32x4 *stage,
+                                            const f32x4 *bias, const f32x4 *ltab, const MfmaWeights<P, HID, NL> &W,
+                                            SpanUv<ST> &uvs, int64_t next_first, int64_t next_end_px) {
+  using Frag = typename P::Frag;
+  const int lane = threadIdx.x;
+  const int mode = a.lat.address;
+  const int n_levels = a.lat.n_levels;
+
+  const int64_t left = end_px - first;
+  const int span = left < 64 * ST ? (int)left : 64 * ST;
+  const int esz = a.out_f16 ? 2 : 4;
+  const __amdgpu_buffer_rsrc_t ors =
+      make_rsrc(reinterpret_cast<const char *>(a.out) + first * a.n_out * esz, (uint32_t)(span * a.n_out * esz));
+
+  if (!NTC_UV_PREFETCH) uvs.load(a.uv, first, end_px);
+  float u[ST], v[ST];
+#pragma unroll
+  for (int q = 0; q < ST; ++q) {
+    u[q] = uvs.u[q];
+    v[q] = uvs.v[q];
   }
 
-  float3 c[NP];
-  bool staged = false;
+  bool staged = false, prefetched = false;
+  int kbx[kMaxLevels], kby[kMaxLevels], kbw[kMaxLevels], kbase[kMaxLevels];
   if (mode == 0) {
-    // taps of this lane group's level; the row reduction of the left/top
-    // taps gives the level's box (left taps in [bx, bx + bw - 2])
-    int ti[NP], tj[NP];
-    float fx[NP], fy[NP];
-    int x0 = 0x7fffffff, x1 = -1, y0 = 0x7fffffff, y1 = -1;
+    float umin = tap_coord(u[0]), umax = umin, vmin = tap_coord(v[0]), vmax = vmin;
 #pragma unroll
-    for (int t = 0; t < NP; ++t) {
-      clamp_tap(u[t], L.fw, L.sx, L.w - 2, ti[t], fx[t]);
-      clamp_tap(v[t], L.fh, L.sy, L.h - 2, tj[t], fy[t]);
-      x0 = min(x0, ti[t]);
-      x1 = max(x1, ti[t]);
-      y0 = min(y0, tj[t]);
-      y1 = max(y1, tj[t]);
+    for (int q = 1; q < ST; ++q) {
+      umin = fminf(umin, tap_coord(u[q]));
+      umax = fmaxf(umax, tap_coord(u[q]));
+      vmin = fminf(vmin, tap_coord(v[q]));
+      vmax = fmaxf(vmax, tap_coord(v[q]));
     }
-    x0 = row_min_i(x0);
-    x1 = row_max_i(x1);
-    y0 = row_min_i(y0);
-    y1 = row_max_i(y1);
-    const int bw = has_level ? x1 - x0 + 2 : 0;
-    const int bh = has_level ? y1 - y0 + 2 : 0;
-    const int cnt = bw * bh;
-    const int c0 = __builtin_amdgcn_readlane(cnt, 0), c1 = __builtin_amdgcn_readlane(cnt, 16);
-    const int c2 = __builtin_amdgcn_readlane(cnt, 32), c3 = __builtin_amdgcn_readlane(cnt, 48);
-    if (c0 + c1 + c2 + c3 <= a.stage_cap) {
+    umin = wave_min(umin);
+    umax = wave_max(umax);
+    vmin = wave_min(vmin);
+    vmax = wave_max(vmax);
+    // lane 4 k + 2 axis + side: tap index of the extreme coordinate
+    const int le = (lane >> 1) & 7;  // level le / 2, axis le % 2
+    const f32x4 tb = (ltab + opaque_zero())[3 * (le >> 1) + (le & 1)];
+    const float ext = (lane & 2) ? ((lane & 1) ? vmax : vmin) : ((lane & 1) ? umax : umin);
+    const int ti = (int)tap_floor(ext, tb[0], tb[1], tb[2]);
+    int cnt[kMaxLevels], total = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k) {
+      kbx[k] = __builtin_amdgcn_readlane(ti, 4 * k);
+      const int ex = __builtin_amdgcn_readlane(ti, 4 * k + 1);
+      kby[k] = __builtin_amdgcn_readlane(ti, 4 * k + 2);
+      const int ey = __builtin_amdgcn_readlane(ti, 4 * k + 3);
+      const bool used = k < n_levels;
+      kbw[k] = used ? ex - kbx[k] + 2 : 0;
+      cnt[k] = used ? kbw[k] * (ey - kby[k] + 2) : 0;
+      kbase[k] = total;
+      total += cnt[k];
+    }
+    if (total <= a.stage_cap) {
       staged = true;
-      const int cnts[4] = {c0, c1, c2, c3};
-      int gbase = 0, my_base = 0;
+      float krcp[kMaxLevels];
+      __amdgpu_buffer_rsrc_t brs[kMaxLevels];
+      int kbpr[kMaxLevels];
 #pragma unroll
       for (int k = 0; k < kMaxLevels; ++k) {
-        if (g == k) my_base = gbase;
-        const int ck = cnts[k];
-        if (ck > 0) {
-          const LevelArgs &Lk = a.lat.lv[k];
-          const __amdgpu_buffer_rsrc_t brs = make_rsrc(Lk.bc1, (uint32_t)(Lk.bw * (Lk.h >> 2)) * 8u);
-          const int kbx = __builtin_amdgcn_readlane(x0, 16 * k);
-          const int kby = __builtin_amdgcn_readlane(y0, 16 * k);
-          const int kbw = __builtin_amdgcn_readlane(bw, 16 * k);
-          const float rcp = __builtin_amdgcn_rcpf((float)kbw);
-          for (int t = lane; t < ck; t += 64) {
-            // exact: (t + 1/2) / bw is at least 1/(2 bw) from an integer and the
-            // reciprocal's relative error (~2^-22) moves it by < 1e-3 / bw
-            const int ty = (int)(((float)t + 0.5f) * rcp);
-            const int tx = t - ty * kbw;
-            const int X = kbx + tx, Y = kby + ty;
-            const auto blk = __builtin_amdgcn_raw_buffer_load_b64(brs, ((Y >> 2) * Lk.bw + (X >> 2)) * 8, 0, 0);
-            const float3 val = texel_f32(bc1_numer(blk[0], blk[1], (uint32_t)(((Y & 3) << 2) | (X & 3))));
-            const f32x4 s4 = {val.x, val.y, val.z, 0.0f};
-            stage[gbase + t] = s4;
-          }
-        }
-        gbase += ck;
+        const f32x4 *tk = ltab + opaque_zero() + 3 * k;
+        const f32x4 eb = tk[2];
+        const unsigned lo = __builtin_amdgcn_readfirstlane(__float_as_uint(eb[0]));
+        const unsigned hi = __builtin_amdgcn_readfirstlane(__float_as_uint(eb[1]));
+        kbpr[k] = __builtin_amdgcn_readfirstlane(__float_as_int(eb[2]));
+        const int hk = __builtin_amdgcn_readfirstlane(__float_as_int(tk[1][3]));
+        brs[k] = make_rsrc((const void *)(((unsigned long long)hi << 32) | lo), (uint32_t)(kbpr[k] * (hk >> 2)) * 8u);
+        krcp[k] = __builtin_amdgcn_rcpf((float)(kbw[k] > 0 ? kbw[k] : 1));
       }
-      __syncthreads();
-      if (has_level) {
+      // texel t of level k: box-relative (t mod bw, t div bw); exact since
+      // (t + 1/2) / bw is at least 1/(2 bw) from an integer and the
+      // reciprocal's relative error (~2^-22) moves it by < 1e-3 / bw
+      auto coords = [&](int k, int t, int &X, int &Y) {
+        const int ty = (int)(((float)t + 0.5f) * krcp[k]);
+        X = kbx[k] + (t - __mul24(ty, kbw[k]));
+        Y = kby[k] + ty;
+      };
+      // footprint texels lie inside the level, so every block is in range
+      auto fetch = [&](int k, int X, int Y) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(brs[k], (__mul24(Y >> 2, kbpr[k]) + (X >> 2)) * 8, 0, 0);
+        return make_uint2(w[0], w[1]);
+      };
+      auto put = [&](int k, int t, int X, int Y, uint2 blk) {
+        const float3 val = texel_f32(bc1_numer(blk.x, blk.y, (uint32_t)(((Y & 3) << 2) | (X & 3))));
+        const f32x4 s4 = {val.x, val.y, val.z, 0.0f};
+        stage[kbase[k] + t] = s4;
+      };
+      // first round of every level, and the second of level 0, in flight
+      // together; lanes without a texel fetch block 0 of their level (the
+      // library points unused levels at level 0, so it always exists)
+      constexpr int NR = kMaxLevels + 1;
+      int RX[NR], RY[NR];
+      uint2 blk[NR];
 #pragma unroll
-        for (int t = 0; t < NP; ++t) {
-          const int r = my_base + (tj[t] - y0) * bw + (ti[t] - x0);
-          const f32x4 t00 = stage[r], t10 = stage[r + 1], t01 = stage[r + bw], t11 = stage[r + bw + 1];
-          c[t] = blend4(make_float3(t00[0], t00[1], t00[2]), make_float3(t10[0], t10[1], t10[2]),
-                        make_float3(t01[0], t01[1], t01[2]), make_float3(t11[0], t11[1], t11[2]), fx[t], fy[t]);
+      for (int r = 0; r < NR; ++r) {
+        const int k = r < kMaxLevels ? r : 0;
+        const int t = r < kMaxLevels ? lane : lane + 64;
+        coords(k, t, RX[r], RY[r]);
+        if (t >= cnt[k]) RX[r] = RY[r] = 0;
+        blk[r] = fetch(k, RX[r], RY[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int k = r < kMaxLevels ? r : 0;
+        const int t = r < kMaxLevels ? lane : lane + 64;
+        if (t < cnt[k]) put(k, t, RX[r], RY[r], blk[r]);
+      }
+      // remaining texels of large footprints
+#pragma unroll
+      for (int k = 0; k < kMaxLevels; ++k) {
+        for (int t = lane + (k == 0 ? 128 : 64); t < cnt[k]; t += 64) {
+          int X, Y;
+          coords(k, t, X, Y);
+          put(k, t, X, Y, fetch(k, X, Y));
         }
       }
-      __syncthreads();
+      if (NTC_UV_PREFETCH && next_first >= 0) {
+        uvs.load(a.uv, next_first, next_end_px);
+        prefetched = true;
+      }
     }
   }
-  if (!staged && has_level) {
-#pragma unroll
-    for (int t = 0; t < NP; ++t) c[t] = sample_direct(L, u[t], v[t], mode);
-  }
+  if (NTC_UV_PREFETCH && !prefetched && next_first >= 0) uvs.load(a.uv, next_first, next_end_px);
 
+  // Sub-spans of 64 pixels: every lane samples all levels of its pixel, the
+  // lane halves exchange operand halves, and the MLP runs on two N-tiles.
+  // (not unrolled: one sub-span's sampling and MLP at a time keeps the
+  // register footprint to that of a single sub-span; the coordinates rotate
+  // through u[0], v[0])
+#pragma unroll 1
+  for (int q = 0; q < ST; ++q) {
+    if (64 * q >= span) break;
+    float xl[8], xh[8];
+    const float uq = u[0], vq = v[0];
 #pragma unroll
-  for (int p = 0; p < 2 * TP; ++p) {
-    Frag bx[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int t = 2 * p + q;
-      const float3 cc = has_level ? c[t] : make_float3(0.f, 0.f, 0.f);
-      bx[q] = P::features(cc.x, cc.y, cc.z, g == 0 ? u[t] : 0.f, g == 0 ? v[t] : 0.f, W.in_scale);
+    for (int i = 0; i + 1 < ST; ++i) {
+      u[i] = u[i + 1];
+      v[i] = v[i + 1];
     }
-    mlp_store2<P, HID, NL>(a, W, wrs, ors, bx, 2 * p);
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k) {
+      float3 c = make_float3(0.f, 0.f, 0.f);
+      if (k < n_levels) {
+        TabLevel Lk;
+        Lk.read(ltab + opaque_zero(), k);
+        if (staged) {
+          int i0, j0;
+          float fx, fy;
+          clamp_tap(tap_coord(uq), Lk.fw, Lk.cx, Lk.wm2, i0, fx);
+          clamp_tap(tap_coord(vq), Lk.fh, Lk.cy, Lk.hm2, j0, fy);
+          // taps lie inside the footprint: r = kbase + (j0 - by) bw + (i0 - bx)
+          const int r = __mul24(j0, kbw[k]) + i0 + (kbase[k] - kby[k] * kbw[k] - kbx[k]);
+          const f32x4 t00 = stage[r], t10 = stage[r + 1], t01 = stage[r + kbw[k]], t11 = stage[r + kbw[k] + 1];
+          c = blend4(make_float3(t00[0], t00[1], t00[2]), make_float3(t10[0], t10[1], t10[2]),
+                     make_float3(t01[0], t01[1], t01[2]), make_float3(t11[0], t11[1], t11[2]), fx, fy);
+        } else {
+          c = sample_direct_t(Lk, uq, vq, mode);
+        }
+      }
+      float *x = k < 2 ? xl : xh;
+      const int o = 3 * (k & 1);
+      x[o] = c.x;
+      x[o + 1] = c.y;
+      x[o + 2] = c.z;
+    }
+    xl[6] = uq;
+    xl[7] = vq;
+    xh[6] = 0.0f;
+    xh[7] = 0.0f;
+    Frag bx[2];
+    bx[0] = P::features(xl, W.in_scale);
+    bx[1] = P::features(xh, W.in_scale);
+    swap_halves<P>(bx[0], bx[1]);
+    // both N-tiles in one MLP pass when the weights leave room for two sets
+    // of accumulators, otherwise one after the other
+    if constexpr (HID >= 64 && NL >= 3 && NTC_WIDE_NT == 1) {
+      const Frag b0[1] = {bx[0]}, b1[1] = {bx[1]};
+      mlp_store<P, HID, NL, 1, VEC4>(a, W, bias, ors, b0, 2 * q);
+      mlp_store<P, HID, NL, 1, VEC4>(a, W, bias, ors, b1, 2 * q + 1);
+    } else {
+      mlp_store<P, HID, NL, 2, VEC4>(a, W, bias, ors, bx, 2 * q);
+    }
   }
 }
 

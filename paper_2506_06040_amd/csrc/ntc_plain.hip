@@ -31,15 +31,22 @@ PackLayout pack_layout(const MlpShape &s, int compute) {
       off = L.b_off[l] + (size_t)rows * 4;
     }
   } else {
-    L.elem_bytes = (compute == 3) ? 1 : 2;
-    const size_t frag = 64 * 8 * (size_t)L.elem_bytes;
+    // 32x32 matrix-core tiles: M-tiles of 32 output rows; K-steps of 16
+    // inputs (FP16, 8 per lane) or 64 inputs (E4M3, 32 per lane).
+    const bool f8 = compute == 3;
+    L.elem_bytes = f8 ? 1 : 2;
+    L.frag_elems = f8 ? 32 : 8;
+    const int kstep = f8 ? 64 : 16;
+    const size_t frag = 64 * (size_t)L.frag_elems * (size_t)L.elem_bytes;
     for (int l = 0; l < Ln; ++l) {
-      L.mt[l] = (l == Ln - 1) ? 1 : s.hid / 16;
-      L.kc[l] = (l == 0) ? 1 : (s.hid >= 32 ? s.hid / 32 : 1);
+      const int rows = (l == Ln - 1) ? s.n_out : s.hid;
+      const int cols = (l == 0) ? s.in_dim : s.hid;
+      L.mt[l] = (rows + 31) / 32;
+      L.kc[l] = (cols + kstep - 1) / kstep;
       L.w_off[l] = align_up(off, 256);
       off = L.w_off[l] + (size_t)L.mt[l] * L.kc[l] * frag;
       L.b_off[l] = align_up(off, 256);
-      off = L.b_off[l] + (size_t)L.mt[l] * 64;
+      off = L.b_off[l] + (size_t)L.mt[l] * 2 * 16 * sizeof(float);
     }
   }
   L.scale_off = align_up(off, 256);
@@ -57,22 +64,32 @@ struct PackArgs {
   int compute;
 };
 
-// Source column of element e (0..7) of lane group g in K-chunk c of layer l
-// of a matrix-core image, or -1 for padding.
-//   layer 0: lane group g carries level g (3 channels); group 0 also u, v.
-//   layer >0: the K order follows the accumulator layout of the previous
-//   layer: element e of group g in chunk c is hidden unit
-//   16 (2c + e/4) + 4g + e%4.
-__device__ __forceinline__ int frag_source_col(const MlpShape &s, int l, int c, int g, int e) {
-  if (l == 0) {
-    const int n_levels = (s.in_dim - 2) / 3;
-    if (e < 3) return g < n_levels ? 3 * g + e : -1;
-    if (g == 0 && e == 3) return 3 * n_levels;
-    if (g == 0 && e == 4) return 3 * n_levels + 1;
-    return -1;
+// Input index fed to K-slot (lane half h, element e) of the first layer:
+// half 0 carries levels 0 and 1 and (u, v), half 1 levels 2 and 3.
+__device__ __forceinline__ int feature_col(int n_levels, int h, int e) {
+  if (e < 6) {
+    const int lvl = 2 * h + (e >= 3 ? 1 : 0);
+    return lvl < n_levels ? 3 * lvl + (e >= 3 ? e - 3 : e) : -1;
   }
-  const int h = 16 * (2 * c + (e >> 2)) + 4 * g + (e & 3);
-  return h < s.hid ? h : -1;
+  if (h == 0 && e == 6) return 3 * n_levels;
+  if (h == 0 && e == 7) return 3 * n_levels + 1;
+  return -1;
+}
+
+// Source column of element e of lane half h in K-step c of layer l, or -1 for
+// padding. Hidden layers take their K order from the accumulator layout of
+// the previous layer (lane half h holds rows 8 j + 4 h + r, j, r < 4, of each
+// 32-row tile):
+//   FP16, K-step 16: element e is unit 32 (c/2) + 16 (c%2) + 8 (e/4) + 4 h + e%4
+//   E4M3, K-step 64: element e is unit 32 (2c + e/16) + 8 ((e%16)/4) + 4 h + e%4
+__device__ __forceinline__ int frag_source_col(const MlpShape &s, bool f8, int l, int c, int h, int e) {
+  if (l == 0) return (f8 && e >= 8) ? -1 : feature_col((s.in_dim - 2) / 3, h, e);
+  int u;
+  if (f8)
+    u = 32 * (2 * c + (e >> 4)) + 8 * ((e & 15) >> 2) + 4 * h + (e & 3);
+  else
+    u = 32 * (c >> 1) + 16 * (c & 1) + 8 * (e >> 2) + 4 * h + (e & 3);
+  return u < s.hid ? u : -1;
 }
 
 // Scales of the E4M3 image: s_w = 448 / max|W_l|, s_a = 448 / act_amax[l];
@@ -151,19 +168,21 @@ __global__ void pack_kernel(PackArgs a, int64_t n_w_elems, int64_t n_elems) {
   }
   if (e < n_w_elems) {
     int64_t r = e;
+    const bool f8 = a.compute == 3;
+    const int E = L.frag_elems;
     for (int l = 0; l < Ln; ++l) {
-      const int64_t nl = (int64_t)L.mt[l] * L.kc[l] * 64 * 8;
+      const int64_t nl = (int64_t)L.mt[l] * L.kc[l] * 64 * E;
       if (r < nl) {
-        const int el = (int)(r & 7);
-        const int lane = (int)((r >> 3) & 63);
-        const int64_t fr = r >> 9;  // frag index = m * kc + c
+        const int el = (int)(r % E);
+        const int lane = (int)((r / E) & 63);
+        const int64_t fr = r / (64 * E);  // frag index = m * kc + c
         const int c = (int)(fr % L.kc[l]), m = (int)(fr / L.kc[l]);
-        const int row = 16 * m + (lane & 15);
-        const int col = frag_source_col(s, l, c, lane >> 4, el);
+        const int row = 32 * m + (lane & 31);
+        const int col = frag_source_col(s, f8, l, c, lane >> 5, el);
         const int rows = a.p.dims[l + 1], cols = a.p.dims[l];
         float v = 0.f;
         if (row < rows && col >= 0 && col < cols) v = a.p.W[l][(int64_t)row * cols + col];
-        if (a.compute == 3) {
+        if (f8) {
           (a.packed + L.w_off[l])[r] = to_e4m3(v * sc[3 * l + 2]);
         } else {
           ((_Float16 *)(a.packed + L.w_off[l]))[r] = (_Float16)v;
@@ -174,13 +193,13 @@ __global__ void pack_kernel(PackArgs a, int64_t n_w_elems, int64_t n_elems) {
     }
     return;
   }
-  // bias fragments: [m][group][4] floats
+  // bias fragments: [m][h][16] floats, element 4 j + r = row 32 m + 8 j + 4 h + r
   int64_t r = e - n_w_elems;
   for (int l = 0; l < Ln; ++l) {
-    const int64_t nb = (int64_t)L.mt[l] * 16;
+    const int64_t nb = (int64_t)L.mt[l] * 32;
     if (r < nb) {
-      const int m = (int)(r / 16), gi = (int)((r / 4) & 3), ri = (int)(r & 3);
-      const int row = 16 * m + 4 * gi + ri;
+      const int m = (int)(r / 32), h = (int)((r / 16) & 1), q = (int)(r & 15);
+      const int row = 32 * m + 8 * (q >> 2) + 4 * h + (q & 3);
       const int rows = a.p.dims[l + 1];
       float v = row < rows ? a.p.b[l][row] : 0.f;
       if (a.compute == 3) v = v * (sc[3 * l + 2] * sc[3 * l + 0]);
@@ -205,9 +224,9 @@ hipError_t launch_pack(const MlpShape &s, const MlpPtrs &p, int compute, const f
     for (int l = 0; l < s.n_layers; ++l) n_all += (int64_t)lay.rows_pad[l] * lay.cols_pad[l] + lay.rows_pad[l];
     n_w = n_all;
   } else {
-    for (int l = 0; l < s.n_layers; ++l) n_w += (int64_t)lay.mt[l] * lay.kc[l] * 64 * 8;
+    for (int l = 0; l < s.n_layers; ++l) n_w += (int64_t)lay.mt[l] * lay.kc[l] * 64 * lay.frag_elems;
     n_all = n_w;
-    for (int l = 0; l < s.n_layers; ++l) n_all += (int64_t)lay.mt[l] * 16;
+    for (int l = 0; l < s.n_layers; ++l) n_all += (int64_t)lay.mt[l] * 32;
   }
   if (compute == 3) {
     hipLaunchKernelGGL(pack_scales_kernel, dim3(s.n_layers), dim3(256), 0, st, a);

@@ -99,7 +99,7 @@ def test_decode_validation(A):
     assert _decode(A, lat, mlp, cfg=cfg) == A.E_SHAPE
     cfg.waves_per_cu, cfg.stage_capacity = 8, 10
     assert _decode(A, lat, mlp, cfg=cfg) == A.E_SHAPE
-    cfg.stage_capacity, cfg.tiles_per_iter = 1024, 3
+    cfg.stage_capacity, cfg.tiles_per_iter = 1024, 1
     assert _decode(A, lat, mlp, cfg=cfg) == A.E_UNSUPPORTED
     # n == 0 enqueues nothing and succeeds without touching the GPU
     assert _decode(A, lat, mlp, n=0) == A.OK
