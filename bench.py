@@ -195,7 +195,10 @@ def main():
             m = ntc.Material(ntc.Latents(lnp, device=dev), ntc.Mlp(Wm, bm, device=dev),
                              I.pixel_uv_torch(sp.side, sp.side, "tiled", dev))
             mats.append(m)
-        plan = ntc.BatchPlan(mats)
+        # tile shapes (work-item size, waves per CU, staging capacity) from
+        # the autotuner; the tuning launches are not part of the timing
+        best, table = ntc.autotune.tune_batched(mats, cache=None)
+        plan = ntc.BatchPlan(mats, ntc.batch_cfg(n_cus=ntc.api._device_cus(dev), **best))
         npx = sum(sp.n for sp in specs)
         ms_one = time_launches(plan.launch, 5, 2)
         g = torch.cuda.CUDAGraph()
@@ -217,7 +220,8 @@ def main():
                                 "per_material_launches_ms": ms_many,
                                 "Gtexel_per_s": npx / ms_graph / 1e6,
                                 "per_material_Gtexel_per_s": npx / ms_many / 1e6,
-                                "waves": plan.header()["n_waves"]}
+                                "waves": plan.header()["n_waves"], "autotuned": best,
+                                "autotune_ms": {json.dumps(c, sort_keys=True): round(ms, 3) for c, ms in table}}
         del mats, plan
 
     cpu = None

@@ -94,12 +94,16 @@ typedef struct {
 } ntc_mlp;
 
 /* Tile configuration of the MFMA decode. Zero fields pick defaults.
- *   waves_per_cu : persistent waves launched per compute unit (1..32)
- *   tiles_per_iter: 64-pixel tiles a wave stages together before running
- *                   the MLP on them (this build: 2)
- *   stage_capacity: texels a wave may stage in LDS per tile (64..4096);
- *                   tiles whose footprint is larger fall back to direct
- *                   block fetches. */
+ *   waves_per_cu : workgroups (one wave each) launched per compute unit
+ *                  (1..1024); each walks every grid-th span, so more than
+ *                  the resident count trades weight reloads for balance
+ *   tiles_per_iter: 64-pixel tiles a wave stages together (a span) before
+ *                   running the MLP on them; fixed when the library is
+ *                   compiled (4 by default), other values give
+ *                   NTC_E_UNSUPPORTED
+ *   stage_capacity: texels a wave may stage in LDS per span (64..4096,
+ *                   default 1024); spans whose footprint is larger fall back
+ *                   to direct block fetches. */
 typedef struct {
     int32_t waves_per_cu;
     int32_t tiles_per_iter;

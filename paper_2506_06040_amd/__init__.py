@@ -10,3 +10,4 @@ from .api import (  # noqa: F401
     NO_SHIFT, PAPER_SHIFT, BatchPlan, Latents, Material, Mlp, NtcDecodeFn, batch_cfg, bc1_decode_texels,
     calibrate_fp8, decode, decode_backward, decode_fn, pack, pack_size, tile_cfg,
 )
+from . import autotune  # noqa: F401,E402

@@ -237,14 +237,16 @@ ntc_status ntc_decode(const ntc_latents *lat, const ntc_mlp *mlp, int32_t comput
   if (!aligned(packed, 256)) return fail(NTC_E_ALIGN, "packed must be 256-byte aligned");
   if (!aligned(uv, 8)) return fail(NTC_E_ALIGN, "uv must be 8-byte aligned");
   if (!aligned(out, 16)) return fail(NTC_E_ALIGN, "out must be 16-byte aligned");
-  int stage_cap = 1024, waves_per_cu = 8, tiles_per_iter = 2;
+  int stage_cap = 1024, waves_per_cu = 8, tiles_per_iter = decode_span_tiles();
   if (cfg) {
     if (cfg->waves_per_cu) waves_per_cu = cfg->waves_per_cu;
     if (cfg->stage_capacity) stage_cap = cfg->stage_capacity;
     if (cfg->tiles_per_iter) tiles_per_iter = cfg->tiles_per_iter;
-    if (tiles_per_iter != 2) return fail(NTC_E_UNSUPPORTED, "tiles_per_iter %d (only 2)", tiles_per_iter);
+    if (tiles_per_iter != decode_span_tiles())
+      return fail(NTC_E_UNSUPPORTED, "tiles_per_iter %d (this build: %d)", tiles_per_iter, decode_span_tiles());
   }
-  if (waves_per_cu < 1 || waves_per_cu > 32) return fail(NTC_E_SHAPE, "waves_per_cu %d outside 1..32", waves_per_cu);
+  if (waves_per_cu < 1 || waves_per_cu > 1024)
+    return fail(NTC_E_SHAPE, "waves_per_cu %d outside 1..1024", waves_per_cu);
   if (stage_cap < 64 || stage_cap > 4096) return fail(NTC_E_SHAPE, "stage_capacity %d outside 64..4096", stage_cap);
   if (n == 0) return ok();
 
@@ -379,7 +381,7 @@ ntc_status setup_batch(const ntc_material *mats, int32_t n_mats, const ntc_batch
     if (cfg->n_cus) cus = cfg->n_cus;
   }
   if (item_px < 64 || item_px > 65536 || (item_px & 63)) return fail(NTC_E_SHAPE, "item_pixels %d", item_px);
-  if (wpc < 1 || wpc > 32) return fail(NTC_E_SHAPE, "waves_per_cu %d outside 1..32", wpc);
+  if (wpc < 1 || wpc > 1024) return fail(NTC_E_SHAPE, "waves_per_cu %d outside 1..1024", wpc);
   if (cap < 64 || cap > 4096) return fail(NTC_E_SHAPE, "stage_capacity %d outside 64..4096", cap);
   if (cus < 1 || cus > 4096) return fail(NTC_E_SHAPE, "n_cus %d", cus);
   b->mats.resize(n_mats);

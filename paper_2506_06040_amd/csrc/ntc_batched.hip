@@ -37,6 +37,7 @@ __device__ __forceinline__ void run_material(const BatchMaterial &M, const Batch
   // earlier instructions, which a single-wave workgroup completes in order
   BiasLds<HID, NL>::fill(bias, a.packed, a.lay, lane);
   LevelTab::fill(ltab, a.lat, lane);
+  W.ready();
   __syncthreads();
   // walk spans of up to ST tiles inside each item; the uv of the next span
   // is prefetched
@@ -48,6 +49,7 @@ __device__ __forceinline__ void run_material(const BatchMaterial &M, const Batch
   int it = it0;
   int64_t tile = items[it0].first_tile;
   uvs.load(a.uv, tile * 64, item_end(it0));
+  uvs.ready();
   while (it < it1) {
     const int64_t end_px = item_end(it);
     int nit = it;

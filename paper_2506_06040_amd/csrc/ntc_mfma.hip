@@ -33,6 +33,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
   W.load(a.packed, a.lay, lane);
   BiasLds<HID, NL>::fill(bias, a.packed, a.lay, lane);
   LevelTab::fill(ltab, a.lat, lane);
+  W.ready();
   __syncthreads();
 
   // XCD-aware numbering: consecutive workgroups land on different XCDs;
@@ -42,7 +43,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
   if ((nb & 7) == 0) vb = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
   const int64_t n_spans = (a.n + SPX - 1) / SPX;
   SpanUv<ST> uvs;
-  if (vb < n_spans) uvs.load(a.uv, (int64_t)vb * SPX, a.n);
+  if (vb < n_spans) {
+    uvs.load(a.uv, (int64_t)vb * SPX, a.n);
+    // completed before the loop, so that the loop is entered with the same
+    // pending loads as its back edge has
+    uvs.ready();
+  }
   for (int64_t it = vb; it < n_spans; it += nb) {
     const int64_t nx = it + nb;
     decode_span<P, HID, NL, ST, VEC4>(a, it * SPX, a.n, stage, bias, ltab, W, uvs, nx < n_spans ? nx * SPX : -1,
@@ -78,6 +84,8 @@ static hipError_t launch_mfma_prec(const DecodeArgs &a, const MlpShape &s, int g
     default: return hipErrorInvalidValue;
   }
 }
+
+int decode_span_tiles() { return kSpanTiles; }
 
 hipError_t launch_decode_mfma(const DecodeArgs &a, const MlpShape &s, int compute, int grid_waves, hipStream_t st) {
   int64_t grid = grid_waves;

@@ -1,27 +1,32 @@
 // Matrix-core tile decode shared by the single-material and the batched
 // kernels.
 //
-// A wavefront decodes spans of 128 pixels (two 64-pixel tiles). Lane
-// l = 32 h + n owns pixels 32 t + n (t < 4) of the span and samples latent
-// levels 2h and 2h + 1 for them:
-//   1. uv of its four pixels (buffer loads, prefetched one span ahead).
-//   2. Bilinear taps on its two levels; clamp-to-edge is applied to the
-//      sampling position (index clamped to [0, w - 2], fraction to [0, 1]),
-//      so the right / lower tap is always the next texel and an edge sample
-//      puts weight 1 on the edge texel, which equals clamping both taps.
-//   3. Bounding box of the taps on every level (DPP row reductions). If the
-//      boxes fit the wave's LDS region, every texel in them is decoded once
-//      (integer BC1 decode, exact numerators scaled to FP32) into LDS and the
-//      taps read four adjacent texels from there; otherwise the taps fetch
-//      their blocks directly.
-//   4. MLP on 32x32 matrix-core tiles: weights are the A operand (32 output
-//      rows per M-tile), pixels the B operand (32 per N-tile), FP32
-//      accumulation initialised with the bias. The 32x32 accumulator leaves
-//      lane 32 h + n with rows 8 j + 4 h + r (j, r < 4) of pixel n; the next
-//      layer's weight columns are permuted at pack time so that those rows
-//      are exactly the K elements the lane must supply as B operand. Layers
-//      chain in registers: only ReLU and the conversion run in between.
-//   5. Sigmoid (hardware exp2 / reciprocal) on the rows that hold outputs,
+// A wavefront decodes spans of 64 ST pixels (ST = NTC_SPAN_TILES):
+//   1. uv of the span (buffer loads, prefetched one span ahead); lane l owns
+//      pixels 64 q + l.
+//   2. Footprint: every tap index is a monotonic function of the coordinate,
+//      so the span's extreme coordinates (wave reductions) give each level's
+//      tap range; 16 lanes evaluate them at once (level x axis x min/max).
+//   3. Staging (clamp addressing, footprint within the LDS region): whole
+//      blocks covering the footprint, one item per texel row of a block
+//      (4 texels), all levels numbered in one sequence so that a single
+//      round of 64 lanes usually covers the span. Each item is decoded with
+//      exact integer arithmetic and written as FP32 texels to LDS. Otherwise,
+//      and for wrap addressing, taps fetch their blocks directly.
+//   4. Sub-spans of 64 pixels: each lane samples all levels of its own pixel
+//      (clamp-to-edge applied to the sampling position: tap clamped to
+//      [0, n - 2], fraction to [0, 1]), converts its 16 feature slots to the
+//      operand type and trades operand halves with the other lane half
+//      (v_permlane32_swap), which gives the B operands of two 32-pixel
+//      N-tiles.
+//   5. MLP on 32x32 matrix-core tiles: weights are the A operand (32 output
+//      rows per M-tile), FP32 accumulation initialised with the bias. The
+//      32x32 accumulator leaves lane 32 h + n with rows 8 j + 4 h + r
+//      (j, r < 4) of pixel n; the next layer's weight columns are permuted at
+//      pack time so that those rows are exactly the K elements the lane must
+//      supply as B operand. Layers chain in registers: only ReLU and the
+//      conversion run in between.
+//   6. Sigmoid (hardware exp2 / reciprocal) on the rows that hold outputs,
 //      buffer stores whose range check drops pixels past the end.
 #pragma once
 
@@ -39,6 +44,9 @@
 #endif
 #ifndef NTC_WIDE_NT  // N-tiles per MLP pass of 64-wide nets with hidden layers
 #define NTC_WIDE_NT 2
+#endif
+#ifndef NTC_STORE_AUX  // cache policy of the output stores (2: non-temporal)
+#define NTC_STORE_AUX 2
 #endif
 #ifndef NTC_UV_PREFETCH  // load the next span's uv during the current span
 #define NTC_UV_PREFETCH 1
@@ -185,13 +193,15 @@ __device__ __forceinline__ void set_dword(typename P::Frag &f, int d, unsigned w
   }
 }
 
-// A zero the compiler cannot see through. Offsetting an LDS table pointer by
-// it on every use keeps loop-invariant code motion from turning the table
-// (bias fragments, level parameters) into registers held across the whole
-// persistent loop; the table is read again where it is used instead.
-__device__ __forceinline__ int opaque_zero() {
-  int z = 0;
-  asm volatile("" : "+s"(z));
+// A zero the compiler cannot see through, computed from a loop-variant
+// `salt`. Offsetting an LDS table pointer by it inside a loop keeps
+// loop-invariant code motion from turning the table (bias fragments, level
+// parameters) into registers held across the loop; the table is read again
+// where it is used instead. The asm is not volatile, so it orders no memory
+// access and the scheduler stays free to interleave the reads.
+__device__ __forceinline__ int opaque_zero(int salt) {
+  int z;
+  asm("s_mov_b32 %0, 0 ; %1" : "=s"(z) : "s"(salt));
   return z;
 }
 
@@ -277,6 +287,27 @@ struct MfmaWeights {
       for (int l = 0; l < NL; ++l) epi[l] = gload(sc + 3 * l + 1);
     }
   }
+  // Wait for the loads here (an empty asm that reads every register). A
+  // persistent loop entered with these loads still pending would carry that
+  // state into its body and wait for the whole vector-memory counter there
+  // on every iteration.
+  __device__ __forceinline__ void ready() const {
+#if defined(__HIP_DEVICE_COMPILE__)  // the constraints exist for the GPU target only
+#pragma unroll
+    for (int m = 0; m < MT; ++m) asm volatile("" ::"v"(w0[m]));
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int c = 0; c < KS; ++c) asm volatile("" ::"v"(wh[h][m][c]));
+#pragma unroll
+    for (int c = 0; c < KS; ++c) asm volatile("" ::"v"(wo[c]));
+#pragma unroll
+    for (int l = 0; l < kMaxLayers; ++l) asm volatile("" ::"v"(epi[l]));
+    asm volatile("" ::"v"(in_scale));
+#endif
+  }
 };
 
 // Left/top tap along one axis, clamp-to-edge: the position x = u f + c
@@ -355,20 +386,17 @@ struct BiasLds {
 
 // MLP over NT N-tiles of 32 pixels (N-tiles t0 .. t0 + NT - 1 of the span) and
 // store. VEC4: the output width is a multiple of 4.
-template <class P, int HID, int NL, int NT, bool VEC4>
-__device__ __forceinline__ void mlp_store(const DecodeArgs &a, const MfmaWeights<P, HID, NL> &W,
-                                          const f32x4 *bias, __amdgpu_buffer_rsrc_t ors,
-                                          const typename P::Frag (&bx)[NT], int t0) {
+template <class P, int HID, int NL, int NT>
+__device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, const f32x4 *bias,
+                                            const typename P::Frag (&bx)[NT], f32x16 (&z)[NT], int salt) {
   using BL = BiasLds<HID, NL>;
   using WT = MfmaWeights<P, HID, NL>;
   constexpr int MT = WT::MT;
   constexpr int KS = WT::KS;
   constexpr int NH = NL - 2;
   using Frag = typename P::Frag;
-  const int lane = threadIdx.x;
-  const int h = lane >> 5;
-  const int n = lane & 31;
-  bias += opaque_zero();
+  const int h = threadIdx.x >> 5;
+  bias += opaque_zero(salt);
 
   f32x16 acc[NT][MT];
 #pragma unroll
@@ -398,23 +426,37 @@ __device__ __forceinline__ void mlp_store(const DecodeArgs &a, const MfmaWeights
 #pragma unroll
   for (int t = 0; t < NT; ++t) P::template next_operands<MT, KS>(acc[t], hb[t], W.epi[NL - 2]);
   const f32x16 bo = BL::get(bias, BL::off_out(), h);
-  const float out_scale = P::kScaled ? W.epi[NL - 1] : 1.0f;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    f32x16 s = P::mma(W.wo[0], hb[t][0], bo);
+#pragma unroll
+    for (int c = 1; c < KS; ++c) s = P::mma(W.wo[c], hb[t][c], s);
+    z[t] = s;
+  }
+}
+
+// Sigmoid of the output pre-activations of NT N-tiles (N-tiles t0 .. t0 +
+// NT - 1 of the span) and store. VEC4: the output width is a multiple of 4.
+template <class P, int NT, bool VEC4>
+__device__ __forceinline__ void store_outputs(const DecodeArgs &a, float out_scale, __amdgpu_buffer_rsrc_t ors,
+                                              const f32x16 (&z)[NT], int t0) {
+  const int lane = threadIdx.x;
+  const int h = lane >> 5;
+  const int n = lane & 31;
   const int n_out = a.n_out;
   const int esz = a.out_f16 ? 2 : 4;
   // row groups j (rows 8 j + 4 h .. + 3) that hold outputs for some lane
   const int nj = (n_out + 7) >> 3;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    f32x16 z = P::mma(W.wo[0], hb[t][0], bo);
-#pragma unroll
-    for (int c = 1; c < KS; ++c) z = P::mma(W.wo[c], hb[t][c], z);
     const int pix = 32 * (t0 + t) + n;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      if (j < nj) {
+      // the first row group always holds outputs: its store is unconditional
+      if (j == 0 || j < nj) {
         f32x4 f;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) f[i] = sigmoid_fast(P::kScaled ? z[4 * j + i] * out_scale : z[4 * j + i]);
+        for (int i = 0; i < 4; ++i) f[i] = sigmoid_fast(P::kScaled ? z[t][4 * j + i] * out_scale : z[t][4 * j + i]);
         const int row = 8 * j + 4 * h;
         // rows past the output width and pixels past the end go beyond the
         // buffer and are dropped by its range check
@@ -424,10 +466,10 @@ __device__ __forceinline__ void mlp_store(const DecodeArgs &a, const MfmaWeights
           if (a.out_f16) {
             const half4_t hv = __builtin_convertvector(f, half4_t);
             __builtin_amdgcn_raw_buffer_store_b64(
-                __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, hv), ors, off, 0, 2);
+                __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, hv), ors, off, 0, NTC_STORE_AUX);
           } else {
             __builtin_amdgcn_raw_buffer_store_b128(
-                __builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, f), ors, off, 0, 2);
+                __builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, f), ors, off, 0, NTC_STORE_AUX);
           }
         } else {
 #pragma unroll
@@ -438,15 +480,26 @@ __device__ __forceinline__ void mlp_store(const DecodeArgs &a, const MfmaWeights
             const int oi = (row + i < n_out) ? off0 + i * esz : 0x7fffffff;
             if (a.out_f16) {
               const _Float16 hi = (_Float16)fi;
-              __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, hi), ors, oi, 0, 2);
+              __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, hi), ors, oi, 0, NTC_STORE_AUX);
             } else {
-              __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(fi), ors, oi, 0, 2);
+              __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(fi), ors, oi, 0, NTC_STORE_AUX);
             }
           }
         }
       }
     }
   }
+}
+
+// MLP over NT N-tiles of 32 pixels (N-tiles t0 .. t0 + NT - 1 of the span) and
+// store.
+template <class P, int HID, int NL, int NT, bool VEC4>
+__device__ __forceinline__ void mlp_store(const DecodeArgs &a, const MfmaWeights<P, HID, NL> &W,
+                                          const f32x4 *bias, __amdgpu_buffer_rsrc_t ors,
+                                          const typename P::Frag (&bx)[NT], int t0, int salt) {
+  f32x16 z[NT];
+  mlp_compute<P, HID, NL, NT>(W, bias, bx, z, salt);
+  store_outputs<P, NT, VEC4>(a, P::kScaled ? W.epi[NL - 1] : 1.0f, ors, z, t0);
 }
 
 
@@ -460,7 +513,9 @@ __device__ __forceinline__ void mlp_store(const DecodeArgs &a, const MfmaWeights
 // (w - 2 and h - 2 as floats, the other integers as their bits). The footprint lanes and the per-pixel taps use
 // the same values.
 struct LevelTab {
-  static constexpr int kCount = 3 * kMaxLevels;
+  static constexpr int kLevelEntries = 3 * kMaxLevels;
+  // followed by two staging records per level, rewritten on every span
+  static constexpr int kCount = kLevelEntries + 2 * kMaxLevels;
   __device__ __forceinline__ static void fill(f32x4 *dst, const LatArgs &lat, int lane) {
 #pragma unroll
     for (int k = 0; k < kMaxLevels; ++k) {
@@ -540,6 +595,13 @@ struct SpanUv {
       v[q] = __uint_as_float(w[1]);
     }
   }
+  // wait for the loads here (an empty asm that reads every coordinate)
+  __device__ __forceinline__ void ready() const {
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+    for (int q = 0; q < ST; ++q) asm volatile("" ::"v"(u[q]), "v"(v[q]));
+#endif
+  }
 };
 
 // Coordinates entering the clamp-mode taps: NaN becomes -2^20 and the range
@@ -596,7 +658,7 @@ __device__ __forceinline__ void swap_halves(typename P::Frag &lo, typename P::Fr
 // addressing, taps fetch their blocks directly.
 template <class P, int HID, int NL, int ST, bool VEC4>
 __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, int64_t end_px, f32x4 *stage,
-                                            const f32x4 *bias, const f32x4 *ltab, const MfmaWeights<P, HID, NL> &W,
+                                            const f32x4 *bias, f32x4 *ltab, const MfmaWeights<P, HID, NL> &W,
                                             SpanUv<ST> &uvs, int64_t next_first, int64_t next_end_px) {
   using Frag = typename P::Frag;
   const int lane = threadIdx.x;
@@ -605,6 +667,7 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
 
   const int64_t left = end_px - first;
   const int span = left < 64 * ST ? (int)left : 64 * ST;
+  const int span_salt = (int)first;
   const int esz = a.out_f16 ? 2 : 4;
   const __amdgpu_buffer_rsrc_t ors =
       make_rsrc(reinterpret_cast<const char *>(a.out) + first * a.n_out * esz, (uint32_t)(span * a.n_out * esz));
@@ -617,8 +680,8 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     v[q] = uvs.v[q];
   }
 
-  bool staged = false, prefetched = false;
-  int kbx[kMaxLevels], kby[kMaxLevels], kbw[kMaxLevels], kbase[kMaxLevels];
+  bool staged = false;
+  int kbw[kMaxLevels], kbase[kMaxLevels];
   if (mode == 0) {
     float umin = tap_coord(u[0]), umax = umin, vmin = tap_coord(v[0]), vmax = vmin;
 #pragma unroll
@@ -632,153 +695,196 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     umax = wave_max(umax);
     vmin = wave_min(vmin);
     vmax = wave_max(vmax);
-    // lane 4 k + 2 axis + side: tap index of the extreme coordinate
+    // lane 4 k + s (k < 4): tap index of an extreme coordinate on level k,
+    // s = 0: left tap of umin, 1: left tap of umax, 2: top tap of vmin,
+    // 3: top tap of vmax
     const int le = (lane >> 1) & 7;  // level le / 2, axis le % 2
-    const f32x4 tb = (ltab + opaque_zero())[3 * (le >> 1) + (le & 1)];
+    const f32x4 tb = (ltab + opaque_zero(span_salt))[3 * (le >> 1) + (le & 1)];
     const float ext = (lane & 2) ? ((lane & 1) ? vmax : vmin) : ((lane & 1) ? umax : umin);
     const int ti = (int)tap_floor(ext, tb[0], tb[1], tb[2]);
-    int cnt[kMaxLevels], total = 0;
+    // every lane of quad k receives the four values of level k
+    const int qbx = __builtin_amdgcn_mov_dpp(ti, 0x00, 0xF, 0xF, false);
+    const int qex = __builtin_amdgcn_mov_dpp(ti, 0x55, 0xF, 0xF, false);
+    const int qby = __builtin_amdgcn_mov_dpp(ti, 0xAA, 0xF, 0xF, false);
+    const int qey = __builtin_amdgcn_mov_dpp(ti, 0xFF, 0xF, 0xF, false);
+    // Staged region of level k: the whole blocks spanning texel columns
+    // [bx, ex + 1] (block columns col0 .. col0 + ncol - 1) on texel rows
+    // [by, ey + 1]. A staging item is one texel row of one block (4 texels);
+    // items are numbered level by level, row-major inside a level, and item
+    // t owns staged texels 4 t .. 4 t + 3, so level k starts at texel
+    // 4 ibase_k and its rows are 4 ncol_k texels wide.
+    const int qcol0 = qbx >> 2;
+    const int qncol = ((qex + 1) >> 2) - qcol0 + 1;
+    const int qnrow = qey - qby + 2;
+    const int qitems = (lane >> 2) < n_levels ? __mul24(qncol, qnrow) : 0;
+    int kitems[kMaxLevels], kib[kMaxLevels], total = 0;
 #pragma unroll
     for (int k = 0; k < kMaxLevels; ++k) {
-      kbx[k] = __builtin_amdgcn_readlane(ti, 4 * k);
-      const int ex = __builtin_amdgcn_readlane(ti, 4 * k + 1);
-      kby[k] = __builtin_amdgcn_readlane(ti, 4 * k + 2);
-      const int ey = __builtin_amdgcn_readlane(ti, 4 * k + 3);
-      const bool used = k < n_levels;
-      kbw[k] = used ? ex - kbx[k] + 2 : 0;
-      cnt[k] = used ? kbw[k] * (ey - kby[k] + 2) : 0;
-      kbase[k] = total;
-      total += cnt[k];
+      kitems[k] = __builtin_amdgcn_readlane(qitems, 4 * k);
+      const int col0 = __builtin_amdgcn_readlane(qcol0, 4 * k);
+      const int by = __builtin_amdgcn_readlane(qby, 4 * k);
+      kbw[k] = 4 * __builtin_amdgcn_readlane(qncol, 4 * k);
+      kib[k] = total;
+      // sampling: texel (i, j) of level k sits at j kbw + i + kbase
+      kbase[k] = 4 * total - by * kbw[k] - 4 * col0;
+      total += kitems[k];
     }
-    if (total <= a.stage_cap) {
+    if (4 * total <= a.stage_cap) {
       staged = true;
-      float krcp[kMaxLevels];
-      __amdgpu_buffer_rsrc_t brs[kMaxLevels];
-      int kbpr[kMaxLevels];
-#pragma unroll
-      for (int k = 0; k < kMaxLevels; ++k) {
-        const f32x4 *tk = ltab + opaque_zero() + 3 * k;
-        const f32x4 eb = tk[2];
-        const unsigned lo = __builtin_amdgcn_readfirstlane(__float_as_uint(eb[0]));
-        const unsigned hi = __builtin_amdgcn_readfirstlane(__float_as_uint(eb[1]));
-        kbpr[k] = __builtin_amdgcn_readfirstlane(__float_as_int(eb[2]));
-        const int hk = __builtin_amdgcn_readfirstlane(__float_as_int(tk[1][3]));
-        brs[k] = make_rsrc((const void *)(((unsigned long long)hi << 32) | lo), (uint32_t)(kbpr[k] * (hk >> 2)) * 8u);
-        krcp[k] = __builtin_amdgcn_rcpf((float)(kbw[k] > 0 ? kbw[k] : 1));
+      // per-level staging records, written by the lead lane of each quad:
+      // {first item, blocks per staged row, 1 / that, first block column}
+      // and {first texel row, blocks per level row, block pointer}
+      f32x4 *srec = ltab + opaque_zero(span_salt) + LevelTab::kLevelEntries;
+      if ((lane & 3) == 0 && lane < 4 * kMaxLevels) {
+        const int k = lane >> 2;
+        const int ib = k == 0 ? kib[0] : (k == 1 ? kib[1] : (k == 2 ? kib[2] : kib[3]));
+        const f32x4 eb = (ltab + opaque_zero(span_salt))[3 * k + 2];
+        srec[2 * k] = (f32x4){__int_as_float(ib), __int_as_float(qncol), __builtin_amdgcn_rcpf((float)qncol),
+                              __int_as_float(qcol0)};
+        srec[2 * k + 1] = (f32x4){__int_as_float(qby), eb[2], eb[0], eb[1]};
       }
-      // texel t of level k: box-relative (t mod bw, t div bw); exact since
-      // (t + 1/2) / bw is at least 1/(2 bw) from an integer and the
-      // reciprocal's relative error (~2^-22) moves it by < 1e-3 / bw
-      auto coords = [&](int k, int t, int &X, int &Y) {
-        const int ty = (int)(((float)t + 0.5f) * krcp[k]);
-        X = kbx[k] + (t - __mul24(ty, kbw[k]));
-        Y = kby[k] + ty;
+      // item t: its block row (blocks, index word) and staged texels; the
+      // row inside the level is (t - first + 1/2) / ncol rounded down, exact
+      // since the reciprocal's relative error (~2^-22) moves a quotient that
+      // is at least 1/(2 ncol) from an integer by < 1e-3 / ncol
+      auto item_fetch = [&](int t, int &Y) {
+        const int k = (t >= kib[1]) + (t >= kib[2]) + (t >= kib[3]);
+        const f32x4 r0 = srec[2 * k], r1 = srec[2 * k + 1];
+        const int tl = t - __float_as_int(r0[0]);
+        const int ncol = __float_as_int(r0[1]);
+        const int row = (int)(((float)tl + 0.5f) * r0[2]);
+        const int col = tl - __mul24(row, ncol);
+        Y = __float_as_int(r1[0]) + row;
+        const uint2 *blk =
+            (const uint2 *)(((unsigned long long)__float_as_uint(r1[3]) << 32) | __float_as_uint(r1[2]));
+        // footprint rows and blocks lie inside the level
+        return gload2u(blk + (__mul24(Y >> 2, __float_as_int(r1[1])) + __float_as_int(r0[3]) + col));
       };
-      // footprint texels lie inside the level, so every block is in range
-      auto fetch = [&](int k, int X, int Y) {
-        const auto w = __builtin_amdgcn_raw_buffer_load_b64(brs[k], (__mul24(Y >> 2, kbpr[k]) + (X >> 2)) * 8, 0, 0);
-        return make_uint2(w[0], w[1]);
-      };
-      auto put = [&](int k, int t, int X, int Y, uint2 blk) {
-        const float3 val = texel_f32(bc1_numer(blk.x, blk.y, (uint32_t)(((Y & 3) << 2) | (X & 3))));
-        const f32x4 s4 = {val.x, val.y, val.z, 0.0f};
-        stage[kbase[k] + t] = s4;
-      };
-      // first round of every level, and the second of level 0, in flight
-      // together; lanes without a texel fetch block 0 of their level (the
-      // library points unused levels at level 0, so it always exists)
-      constexpr int NR = kMaxLevels + 1;
-      int RX[NR], RY[NR];
-      uint2 blk[NR];
+      auto item_put = [&](int t, int Y, uint2 b) {
+        const uint32_t pos = (uint32_t)(Y & 3) << 2;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int k = r < kMaxLevels ? r : 0;
-        const int t = r < kMaxLevels ? lane : lane + 64;
-        coords(k, t, RX[r], RY[r]);
-        if (t >= cnt[k]) RX[r] = RY[r] = 0;
-        blk[r] = fetch(k, RX[r], RY[r]);
-      }
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int k = r < kMaxLevels ? r : 0;
-        const int t = r < kMaxLevels ? lane : lane + 64;
-        if (t < cnt[k]) put(k, t, RX[r], RY[r], blk[r]);
-      }
-      // remaining texels of large footprints
-#pragma unroll
-      for (int k = 0; k < kMaxLevels; ++k) {
-        for (int t = lane + (k == 0 ? 128 : 64); t < cnt[k]; t += 64) {
-          int X, Y;
-          coords(k, t, X, Y);
-          put(k, t, X, Y, fetch(k, X, Y));
+        for (int i = 0; i < 4; ++i) {
+          const float3 val = texel_f32(bc1_numer(b.x, b.y, pos + i));
+          stage[4 * t + i] = (f32x4){val.x, val.y, val.z, 0.0f};
         }
+      };
+      {
+        int Y = 0;
+        uint2 b = make_uint2(0u, 0u);
+        if (lane < total) b = item_fetch(lane, Y);
+        if (lane < total) item_put(lane, Y, b);
       }
-      if (NTC_UV_PREFETCH && next_first >= 0) {
-        uvs.load(a.uv, next_first, next_end_px);
-        prefetched = true;
+      for (int t = lane + 64; t < total; t += 64) {
+        int Y;
+        const uint2 b = item_fetch(t, Y);
+        item_put(t, Y, b);
       }
     }
   }
-  if (NTC_UV_PREFETCH && !prefetched && next_first >= 0) uvs.load(a.uv, next_first, next_end_px);
-
   // Sub-spans of 64 pixels: every lane samples all levels of its pixel, the
   // lane halves exchange operand halves, and the MLP runs on two N-tiles.
-  // (not unrolled: one sub-span's sampling and MLP at a time keeps the
-  // register footprint to that of a single sub-span; the coordinates rotate
-  // through u[0], v[0])
-#pragma unroll 1
-  for (int q = 0; q < ST; ++q) {
-    if (64 * q >= span) break;
-    float xl[8], xh[8];
-    const float uq = u[0], vq = v[0];
+  auto rotate = [&]() {
 #pragma unroll
     for (int i = 0; i + 1 < ST; ++i) {
       u[i] = u[i + 1];
       v[i] = v[i + 1];
     }
+  };
+  auto to_operands = [&](float (&xl)[8], float (&xh)[8], float uq, float vq, Frag (&bx)[2]) {
+    xl[6] = uq;
+    xl[7] = vq;
+    xh[6] = 0.0f;
+    xh[7] = 0.0f;
+    bx[0] = P::features(xl, W.in_scale);
+    bx[1] = P::features(xh, W.in_scale);
+    swap_halves<P>(bx[0], bx[1]);
+  };
+  auto put3 = [](float (&xl)[8], float (&xh)[8], int k, float3 c) {
+    float *x = k < 2 ? xl : xh;
+    const int o = 3 * (k & 1);
+    x[o] = c.x;
+    x[o + 1] = c.y;
+    x[o + 2] = c.z;
+  };
+  // MLP and store of sub-span q (`salt` varies from one call site and span
+  // to the next, see opaque_zero)
+  auto mlp = [&](const Frag (&bx)[2], int q, int salt) {
+    // both N-tiles in one MLP pass when the weights leave room for two sets
+    // of accumulators, otherwise one after the other
+    if constexpr (HID >= 64 && NL >= 3 && NTC_WIDE_NT == 1) {
+      const Frag b0[1] = {bx[0]}, b1[1] = {bx[1]};
+      mlp_store<P, HID, NL, 1, VEC4>(a, W, bias, ors, b0, 2 * q, salt);
+      mlp_store<P, HID, NL, 1, VEC4>(a, W, bias, ors, b1, 2 * q + 1, salt + 1);
+    } else {
+      mlp_store<P, HID, NL, 2, VEC4>(a, W, bias, ors, bx, 2 * q, salt);
+    }
+  };
+
+  if (staged) {
+    // The next span's uv is requested only now: the vector-memory counter
+    // completes in order, so a load issued before the staging fetches would be
+    // waited for together with them. After it come exactly the stores of the
+    // ST sub-spans below (all of them run, also past the end of a short span,
+    // whose stores the range check drops): that fixed count lets the wait
+    // for these uv at the next span leave the stores in flight.
+    if (NTC_UV_PREFETCH && next_first >= 0) uvs.load(a.uv, next_first, next_end_px);
+#pragma unroll
+    for (int q = 0; q < ST; ++q) {
+      float xl[8], xh[8];
+      const float uq = u[0], vq = v[0];
+      rotate();
+#pragma unroll
+      for (int k = 0; k < kMaxLevels; ++k) {
+        float3 c = make_float3(0.f, 0.f, 0.f);
+        if (k < n_levels) {
+          TabLevel Lk;
+          Lk.read(ltab + opaque_zero(span_salt + q), k);
+          int i0, j0;
+          float fx, fy;
+          clamp_tap(tap_coord(uq), Lk.fw, Lk.cx, Lk.wm2, i0, fx);
+          clamp_tap(tap_coord(vq), Lk.fh, Lk.cy, Lk.hm2, j0, fy);
+          // taps lie inside the staged region of the level
+          const int r = __mul24(j0, kbw[k]) + i0 + kbase[k];
+          const f32x4 t00 = stage[r], t10 = stage[r + 1], t01 = stage[r + kbw[k]], t11 = stage[r + kbw[k] + 1];
+          c = blend4(make_float3(t00[0], t00[1], t00[2]), make_float3(t10[0], t10[1], t10[2]),
+                     make_float3(t01[0], t01[1], t01[2]), make_float3(t11[0], t11[1], t11[2]), fx, fy);
+        }
+        put3(xl, xh, k, c);
+      }
+      Frag bx[2];
+      to_operands(xl, xh, uq, vq, bx);
+      mlp(bx, q, span_salt + 2 * q);
+    }
+    return;
+  }
+
+  // Direct block fetches (footprint beyond the LDS region, or wrap
+  // addressing); one sub-span at a time.
+#pragma unroll 1
+  for (int q = 0; q < ST; ++q) {
+    if (64 * q >= span) break;
+    float xl[8], xh[8];
+    const float uq = u[0], vq = v[0];
+    rotate();
 #pragma unroll
     for (int k = 0; k < kMaxLevels; ++k) {
       float3 c = make_float3(0.f, 0.f, 0.f);
       if (k < n_levels) {
         TabLevel Lk;
-        Lk.read(ltab + opaque_zero(), k);
-        if (staged) {
-          int i0, j0;
-          float fx, fy;
-          clamp_tap(tap_coord(uq), Lk.fw, Lk.cx, Lk.wm2, i0, fx);
-          clamp_tap(tap_coord(vq), Lk.fh, Lk.cy, Lk.hm2, j0, fy);
-          // taps lie inside the footprint: r = kbase + (j0 - by) bw + (i0 - bx)
-          const int r = __mul24(j0, kbw[k]) + i0 + (kbase[k] - kby[k] * kbw[k] - kbx[k]);
-          const f32x4 t00 = stage[r], t10 = stage[r + 1], t01 = stage[r + kbw[k]], t11 = stage[r + kbw[k] + 1];
-          c = blend4(make_float3(t00[0], t00[1], t00[2]), make_float3(t10[0], t10[1], t10[2]),
-                     make_float3(t01[0], t01[1], t01[2]), make_float3(t11[0], t11[1], t11[2]), fx, fy);
-        } else {
-          c = sample_direct_t(Lk, uq, vq, mode);
-        }
+        Lk.read(ltab + opaque_zero(q), k);
+        c = sample_direct_t(Lk, uq, vq, mode);
       }
-      float *x = k < 2 ? xl : xh;
-      const int o = 3 * (k & 1);
-      x[o] = c.x;
-      x[o + 1] = c.y;
-      x[o + 2] = c.z;
+      put3(xl, xh, k, c);
     }
-    xl[6] = uq;
-    xl[7] = vq;
-    xh[6] = 0.0f;
-    xh[7] = 0.0f;
     Frag bx[2];
-    bx[0] = P::features(xl, W.in_scale);
-    bx[1] = P::features(xh, W.in_scale);
-    swap_halves<P>(bx[0], bx[1]);
-    // both N-tiles in one MLP pass when the weights leave room for two sets
-    // of accumulators, otherwise one after the other
-    if constexpr (HID >= 64 && NL >= 3 && NTC_WIDE_NT == 1) {
-      const Frag b0[1] = {bx[0]}, b1[1] = {bx[1]};
-      mlp_store<P, HID, NL, 1, VEC4>(a, W, bias, ors, b0, 2 * q);
-      mlp_store<P, HID, NL, 1, VEC4>(a, W, bias, ors, b1, 2 * q + 1);
-    } else {
-      mlp_store<P, HID, NL, 2, VEC4>(a, W, bias, ors, bx, 2 * q);
-    }
+    to_operands(xl, xh, uq, vq, bx);
+    mlp(bx, q, 2 * q);
+  }
+  // the next span's uv, completed here: this path then leaves no pending
+  // load behind and the wait state where the paths join is the staged one
+  if (NTC_UV_PREFETCH && next_first >= 0) {
+    uvs.load(a.uv, next_first, next_end_px);
+    uvs.ready();
   }
 }
 

@@ -95,7 +95,7 @@ def test_decode_validation(A):
     bad.shift[1][0] = 3.0
     assert _decode(A, bad, mlp) == A.E_SHAPE
     cfg = A.ntc_tile_cfg()
-    cfg.waves_per_cu = 99
+    cfg.waves_per_cu = 2000
     assert _decode(A, lat, mlp, cfg=cfg) == A.E_SHAPE
     cfg.waves_per_cu, cfg.stage_capacity = 8, 10
     assert _decode(A, lat, mlp, cfg=cfg) == A.E_SHAPE

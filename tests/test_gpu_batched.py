@@ -97,3 +97,26 @@ def test_c5_64_materials_equal_per_material():
         ref = O.decode(O.Latents(lat_np, shift=I.PAPER_SHIFT), O.Mlp(Ws, bs), uv)
         got = mats[i].out[torch.from_numpy(idx).cuda()].cpu().numpy()
         assert np.max(np.abs(got - ref)) <= 2e-3, i
+
+
+def test_autotuned_plan_equals_per_material(tmp_path):
+    """The autotuner times its candidates, caches the winner, and the plan it
+    builds decodes exactly like per-material launches."""
+    ntc = _ntc()
+    mats, _ = _materials(_small_specs())
+    cache = str(tmp_path / "tune.json")
+    cands = [dict(item_pixels=4096, waves_per_cu=8, stage_capacity=512),
+             dict(item_pixels=16384, waves_per_cu=4, stage_capacity=1024)]
+    best, table = ntc.autotune.tune_batched(mats, candidates=cands, cache=cache, reps=2)
+    assert best in cands and len(table) == 2 and all(ms > 0 for _, ms in table)
+    again, _ = ntc.autotune.tune_batched(mats, candidates=cands[:1], cache=cache)
+    assert again == best  # served from the cache
+    plan = ntc.autotune.tuned_batch_plan(mats, cache=cache, candidates=cands)
+    for m in mats:
+        m.out.fill_(-1.0)
+    plan.launch()
+    torch.cuda.synchronize()
+    got = [m.out.clone() for m in mats]
+    for m, g in zip(mats, got):
+        ref = ntc.decode(m.lat, m.mlp, m.uv, compute="f16", packed=m.packed)
+        assert torch.equal(g, ref)
