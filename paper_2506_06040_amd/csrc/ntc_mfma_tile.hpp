@@ -45,6 +45,15 @@
 #ifndef NTC_WIDE_NT  // N-tiles per MLP pass of 64-wide nets with hidden layers
 #define NTC_WIDE_NT 2
 #endif
+#ifndef NTC_STAGED_UNROLL  // unroll the staged sub-span loop (exact memory-wait counts)
+#define NTC_STAGED_UNROLL 1
+#endif
+#define NTC_PRAGMA(x) _Pragma(#x)
+#if NTC_STAGED_UNROLL
+#define NTC_UNROLL_STAGED NTC_PRAGMA(unroll)
+#else
+#define NTC_UNROLL_STAGED NTC_PRAGMA(unroll 1)
+#endif
 #ifndef NTC_STORE_AUX  // cache policy of the output stores (2: non-temporal)
 #define NTC_STORE_AUX 2
 #endif
@@ -131,6 +140,16 @@ __device__ __forceinline__ int pack4_e4m3(float a, float b, float c, float d) {
   return __builtin_amdgcn_cvt_pk_fp8_f32(sat448(c), sat448(d), w, true);
 }
 
+// ReLU of scaled values (s > 0, so max(v, 0) s = max(v s, 0)) and E4M3
+// saturation in one median: med3(v s, 0, 448).
+__device__ __forceinline__ int pack4_relu_e4m3(float a, float b, float c, float d) {
+  const float lo = 0.0f, hi = 448.0f;
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_fmed3f(a, lo, hi), __builtin_amdgcn_fmed3f(b, lo, hi), 0,
+                                          false);
+  return __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_fmed3f(c, lo, hi), __builtin_amdgcn_fmed3f(d, lo, hi), w,
+                                         true);
+}
+
 // E4M3 operands, 32x32x64 tiles (full-rate scaled form with unit block
 // scales): a K-step is 64 inputs, 32 bytes per lane.
 struct PrecF8 {
@@ -160,8 +179,7 @@ struct PrecF8 {
           const f32x16 &v = acc[2 * c + q];
 #pragma unroll
           for (int w = 0; w < 4; ++w)
-            hb[c][4 * q + w] = pack4_e4m3(fmaxf(v[4 * w], 0.f) * s, fmaxf(v[4 * w + 1], 0.f) * s,
-                                          fmaxf(v[4 * w + 2], 0.f) * s, fmaxf(v[4 * w + 3], 0.f) * s);
+            hb[c][4 * q + w] = pack4_relu_e4m3(v[4 * w] * s, v[4 * w + 1] * s, v[4 * w + 2] * s, v[4 * w + 3] * s);
         } else {
 #pragma unroll
           for (int w = 0; w < 4; ++w) hb[c][4 * q + w] = 0;
@@ -445,18 +463,23 @@ __device__ __forceinline__ void store_outputs(const DecodeArgs &a, float out_sca
   const int n = lane & 31;
   const int n_out = a.n_out;
   const int esz = a.out_f16 ? 2 : 4;
-  // row groups j (rows 8 j + 4 h .. + 3) that hold outputs for some lane
-  const int nj = (n_out + 7) >> 3;
+  // Row groups j (rows 8 j + 4 h .. + 3) that hold outputs for some lane:
+  // the first always (its store is unconditional), the second when there are
+  // more than 8 outputs (at most 16). The sigmoid of the second group reads
+  // its inputs through an empty asm inside the branch, so that the compiler
+  // does not evaluate its transcendentals ahead of the branch.
+  const bool two_groups = n_out > 8;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int pix = 32 * (t0 + t) + n;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      // the first row group always holds outputs: its store is unconditional
-      if (j == 0 || j < nj) {
+    for (int j = 0; j < 2; ++j) {
+      if (j == 0 || two_groups) {
+        f32x4 zj = {z[t][4 * j], z[t][4 * j + 1], z[t][4 * j + 2], z[t][4 * j + 3]};
+        if (j > 0) asm volatile("" : "+v"(zj));
         f32x4 f;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) f[i] = sigmoid_fast(P::kScaled ? z[t][4 * j + i] * out_scale : z[t][4 * j + i]);
+        for (int i = 0; i < 4; ++i) f[i] = sigmoid_fast(P::kScaled ? zj[i] * out_scale : zj[i]);
         const int row = 8 * j + 4 * h;
         // rows past the output width and pixels past the end go beyond the
         // buffer and are dropped by its range check
@@ -828,7 +851,7 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     // whose stores the range check drops): that fixed count lets the wait
     // for these uv at the next span leave the stores in flight.
     if (NTC_UV_PREFETCH && next_first >= 0) uvs.load(a.uv, next_first, next_end_px);
-#pragma unroll
+    NTC_UNROLL_STAGED
     for (int q = 0; q < ST; ++q) {
       float xl[8], xh[8];
       const float uq = u[0], vq = v[0];
