@@ -413,7 +413,7 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
   constexpr int KS = WT::KS;
   constexpr int NH = NL - 2;
   using Frag = typename P::Frag;
-  const int h = threadIdx.x >> 5;
+  const int h = (threadIdx.x & 63) >> 5;
   bias += opaque_zero(salt);
 
   f32x16 acc[NT][MT];
@@ -458,7 +458,7 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
 template <class P, int NT, bool VEC4>
 __device__ __forceinline__ void store_outputs(const DecodeArgs &a, float out_scale, __amdgpu_buffer_rsrc_t ors,
                                               const f32x16 (&z)[NT], int t0) {
-  const int lane = threadIdx.x;
+  const int lane = (threadIdx.x & 63);
   const int h = lane >> 5;
   const int n = lane & 31;
   const int n_out = a.n_out;
@@ -606,7 +606,7 @@ template <int ST>
 struct SpanUv {
   float u[ST], v[ST];
   __device__ __forceinline__ void load(const float2 *uv, int64_t first_px, int64_t end_px) {
-    const int lane = threadIdx.x;
+    const int lane = (threadIdx.x & 63);
     const int64_t left = end_px - first_px;
     const int span = left < 64 * ST ? (int)left : 64 * ST;
     const __amdgpu_buffer_rsrc_t urs = make_rsrc(uv + first_px, (uint32_t)span * 8u);
@@ -666,34 +666,226 @@ __device__ __forceinline__ void swap_halves(typename P::Frag &lo, typename P::Fr
   }
 }
 
-// Decode one span of up to 64 ST pixels starting at pixel `first` (uv
-// already in uvs) and ending before end_px: footprint, staging, sampling,
-// MLP, store. The uv of the next span (next_first < 0: none) is loaded once
-// this span's block fetches are in flight, so that its latency overlaps the
-// work of the span.
-//
-// Clamp addressing: the taps of every level are monotonic in (u, v), so the
+// Footprint and staging of one span whose lane coordinates are u, v (clamp
+// addressing). The taps of every level are monotonic in (u, v), so the
 // span's footprint on level k is spanned by the taps of the extreme
 // coordinates, computed by 16 lanes in parallel (level, axis, min / max). If
-// the four footprints fit the LDS region (stage_cap texels), every texel in
-// them is decoded once into LDS (exact integer BC1 decode, scaled to FP32)
-// and the pixels read their four taps from there; otherwise, and for wrap
-// addressing, taps fetch their blocks directly.
+// the footprints fit the LDS region (stage_cap texels), every texel in them
+// is decoded once into `stage` (exact integer BC1 decode, scaled to FP32) and
+// the function returns true with kbw / kbase locating texel (i, j) of level
+// k at j kbw[k] + i + kbase[k]. `srec` is this wave's staging record area
+// (2 entries per level), `salt` a value that changes from span to span (see
+// opaque_zero).
+template <int ST>
+__device__ __forceinline__ bool stage_span(const DecodeArgs &a, const float (&u)[ST], const float (&v)[ST],
+                                           f32x4 *stage, const f32x4 *ltab, f32x4 *srec, int salt,
+                                           int (&kbw)[kMaxLevels], int (&kbase)[kMaxLevels]) {
+  const int lane = threadIdx.x & 63;
+  const int n_levels = a.lat.n_levels;
+  if (a.lat.address != 0) return false;
+  float umin = tap_coord(u[0]), umax = umin, vmin = tap_coord(v[0]), vmax = vmin;
+#pragma unroll
+  for (int q = 1; q < ST; ++q) {
+    umin = fminf(umin, tap_coord(u[q]));
+    umax = fmaxf(umax, tap_coord(u[q]));
+    vmin = fminf(vmin, tap_coord(v[q]));
+    vmax = fmaxf(vmax, tap_coord(v[q]));
+  }
+  umin = wave_min(umin);
+  umax = wave_max(umax);
+  vmin = wave_min(vmin);
+  vmax = wave_max(vmax);
+  // lane 4 k + s (k < 4): tap index of an extreme coordinate on level k,
+  // s = 0: left tap of umin, 1: left tap of umax, 2: top tap of vmin,
+  // 3: top tap of vmax
+  const int le = (lane >> 1) & 7;  // level le / 2, axis le % 2
+  const f32x4 tb = (ltab + opaque_zero(salt))[3 * (le >> 1) + (le & 1)];
+  const float ext = (lane & 2) ? ((lane & 1) ? vmax : vmin) : ((lane & 1) ? umax : umin);
+  const int ti = (int)tap_floor(ext, tb[0], tb[1], tb[2]);
+  // every lane of quad k receives the four values of level k
+  const int qbx = __builtin_amdgcn_mov_dpp(ti, 0x00, 0xF, 0xF, false);
+  const int qex = __builtin_amdgcn_mov_dpp(ti, 0x55, 0xF, 0xF, false);
+  const int qby = __builtin_amdgcn_mov_dpp(ti, 0xAA, 0xF, 0xF, false);
+  const int qey = __builtin_amdgcn_mov_dpp(ti, 0xFF, 0xF, 0xF, false);
+  // Staged region of level k: the whole blocks spanning texel columns
+  // [bx, ex + 1] (block columns col0 .. col0 + ncol - 1) on texel rows
+  // [by, ey + 1]. A staging item is one texel row of one block (4 texels);
+  // items are numbered level by level, row-major inside a level, and item
+  // t owns staged texels 4 t .. 4 t + 3, so level k starts at texel
+  // 4 ibase_k and its rows are 4 ncol_k texels wide.
+  const int qcol0 = qbx >> 2;
+  const int qncol = ((qex + 1) >> 2) - qcol0 + 1;
+  const int qnrow = qey - qby + 2;
+  const int qitems = (lane >> 2) < n_levels ? __mul24(qncol, qnrow) : 0;
+  int kib[kMaxLevels], total = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxLevels; ++k) {
+    const int items = __builtin_amdgcn_readlane(qitems, 4 * k);
+    const int col0 = __builtin_amdgcn_readlane(qcol0, 4 * k);
+    const int by = __builtin_amdgcn_readlane(qby, 4 * k);
+    kbw[k] = 4 * __builtin_amdgcn_readlane(qncol, 4 * k);
+    kib[k] = total;
+    kbase[k] = 4 * total - by * kbw[k] - 4 * col0;
+    total += items;
+  }
+  if (4 * total > a.stage_cap) return false;
+  // per-level staging records, written by the lead lane of each quad:
+  // {first item, blocks per staged row, 1 / that, first block column}
+  // and {first texel row, blocks per level row, block pointer}
+  srec += opaque_zero(salt);
+  if ((lane & 3) == 0 && lane < 4 * kMaxLevels) {
+    const int k = lane >> 2;
+    const int ib = k == 0 ? kib[0] : (k == 1 ? kib[1] : (k == 2 ? kib[2] : kib[3]));
+    const f32x4 eb = (ltab + opaque_zero(salt))[3 * k + 2];
+    srec[2 * k] = (f32x4){__int_as_float(ib), __int_as_float(qncol), __builtin_amdgcn_rcpf((float)qncol),
+                          __int_as_float(qcol0)};
+    srec[2 * k + 1] = (f32x4){__int_as_float(qby), eb[2], eb[0], eb[1]};
+  }
+  // item t: its block row (blocks, index word) and staged texels; the row
+  // inside the level is (t - first + 1/2) / ncol rounded down, exact since
+  // the reciprocal's relative error (~2^-22) moves a quotient that is at
+  // least 1/(2 ncol) from an integer by < 1e-3 / ncol
+  auto item_fetch = [&](int t, int &Y) {
+    const int k = (t >= kib[1]) + (t >= kib[2]) + (t >= kib[3]);
+    const f32x4 r0 = srec[2 * k], r1 = srec[2 * k + 1];
+    const int tl = t - __float_as_int(r0[0]);
+    const int ncol = __float_as_int(r0[1]);
+    const int row = (int)(((float)tl + 0.5f) * r0[2]);
+    const int col = tl - __mul24(row, ncol);
+    Y = __float_as_int(r1[0]) + row;
+    const uint2 *blk = (const uint2 *)(((unsigned long long)__float_as_uint(r1[3]) << 32) | __float_as_uint(r1[2]));
+    // footprint rows and blocks lie inside the level
+    return gload2u(blk + (__mul24(Y >> 2, __float_as_int(r1[1])) + __float_as_int(r0[3]) + col));
+  };
+  auto item_put = [&](int t, int Y, uint2 b) {
+    const uint32_t pos = (uint32_t)(Y & 3) << 2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float3 val = texel_f32(bc1_numer(b.x, b.y, pos + i));
+      stage[4 * t + i] = (f32x4){val.x, val.y, val.z, 0.0f};
+    }
+  };
+  {
+    int Y = 0;
+    uint2 b = make_uint2(0u, 0u);
+    if (lane < total) b = item_fetch(lane, Y);
+    if (lane < total) item_put(lane, Y, b);
+  }
+  for (int t = lane + 64; t < total; t += 64) {
+    int Y;
+    const uint2 b = item_fetch(t, Y);
+    item_put(t, Y, b);
+  }
+  return true;
+}
+
+// Operands of the pixel (uq, vq): its 16 feature slots (levels 0, 1 and
+// (u, v) in the half-0 slots, levels 2, 3 in the half-1 slots), converted to
+// the operand type and exchanged between the lane halves (swap_halves): bx[0]
+// then feeds the N-tile of lanes 0..31's pixels, bx[1] that of lanes 32..63.
+template <class P>
+__device__ __forceinline__ void pixel_operands(float (&xl)[8], float (&xh)[8], float uq, float vq, float in_scale,
+                                               typename P::Frag (&bx)[2]) {
+  xl[6] = uq;
+  xl[7] = vq;
+  xh[6] = 0.0f;
+  xh[7] = 0.0f;
+  bx[0] = P::features(xl, in_scale);
+  bx[1] = P::features(xh, in_scale);
+  swap_halves<P>(bx[0], bx[1]);
+}
+
+__device__ __forceinline__ void put_level(float (&xl)[8], float (&xh)[8], int k, float3 c) {
+  float *x = k < 2 ? xl : xh;
+  const int o = 3 * (k & 1);
+  x[o] = c.x;
+  x[o + 1] = c.y;
+  x[o + 2] = c.z;
+}
+
+// Operands of the pixel (uq, vq) from the staged texels.
+template <class P>
+__device__ __forceinline__ void staged_operands(const DecodeArgs &a, const f32x4 *stage, const f32x4 *ltab,
+                                                const int (&kbw)[kMaxLevels], const int (&kbase)[kMaxLevels],
+                                                float uq, float vq, float in_scale, int salt,
+                                                typename P::Frag (&bx)[2]) {
+  float xl[8], xh[8];
+#pragma unroll
+  for (int k = 0; k < kMaxLevels; ++k) {
+    float3 c = make_float3(0.f, 0.f, 0.f);
+    if (k < a.lat.n_levels) {
+      TabLevel Lk;
+      Lk.read(ltab + opaque_zero(salt), k);
+      int i0, j0;
+      float fx, fy;
+      clamp_tap(tap_coord(uq), Lk.fw, Lk.cx, Lk.wm2, i0, fx);
+      clamp_tap(tap_coord(vq), Lk.fh, Lk.cy, Lk.hm2, j0, fy);
+      // taps lie inside the staged region of the level
+      const int r = __mul24(j0, kbw[k]) + i0 + kbase[k];
+      const f32x4 t00 = stage[r], t10 = stage[r + 1], t01 = stage[r + kbw[k]], t11 = stage[r + kbw[k] + 1];
+      c = blend4(make_float3(t00[0], t00[1], t00[2]), make_float3(t10[0], t10[1], t10[2]),
+                 make_float3(t01[0], t01[1], t01[2]), make_float3(t11[0], t11[1], t11[2]), fx, fy);
+    }
+    put_level(xl, xh, k, c);
+  }
+  pixel_operands<P>(xl, xh, uq, vq, in_scale, bx);
+}
+
+// Operands of the pixel (uq, vq) with direct block fetches (footprint beyond
+// the LDS region, or wrap addressing).
+template <class P>
+__device__ __forceinline__ void direct_operands(const DecodeArgs &a, const f32x4 *ltab, float uq, float vq,
+                                                float in_scale, int salt, typename P::Frag (&bx)[2]) {
+  float xl[8], xh[8];
+#pragma unroll
+  for (int k = 0; k < kMaxLevels; ++k) {
+    float3 c = make_float3(0.f, 0.f, 0.f);
+    if (k < a.lat.n_levels) {
+      TabLevel Lk;
+      Lk.read(ltab + opaque_zero(salt), k);
+      c = sample_direct_t(Lk, uq, vq, a.lat.address);
+    }
+    put_level(xl, xh, k, c);
+  }
+  pixel_operands<P>(xl, xh, uq, vq, in_scale, bx);
+}
+
+// MLP and store of sub-span q of a span (two N-tiles of 32 pixels).
+template <class P, int HID, int NL, bool VEC4>
+__device__ __forceinline__ void subspan_mlp(const DecodeArgs &a, const MfmaWeights<P, HID, NL> &W, const f32x4 *bias,
+                                            __amdgpu_buffer_rsrc_t ors, const typename P::Frag (&bx)[2], int q,
+                                            int salt) {
+  using Frag = typename P::Frag;
+  // both N-tiles in one MLP pass when the weights leave room for two sets of
+  // accumulators, otherwise one after the other
+  if constexpr (HID >= 64 && NL >= 3 && NTC_WIDE_NT == 1) {
+    const Frag b0[1] = {bx[0]}, b1[1] = {bx[1]};
+    mlp_store<P, HID, NL, 1, VEC4>(a, W, bias, ors, b0, 2 * q, salt);
+    mlp_store<P, HID, NL, 1, VEC4>(a, W, bias, ors, b1, 2 * q + 1, salt + 1);
+  } else {
+    mlp_store<P, HID, NL, 2, VEC4>(a, W, bias, ors, bx, 2 * q, salt);
+  }
+}
+
+// Output resource of a span: stores past `span` pixels are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_out(const DecodeArgs &a, int64_t first, int span) {
+  const int esz = a.out_f16 ? 2 : 4;
+  return make_rsrc(reinterpret_cast<const char *>(a.out) + first * a.n_out * esz, (uint32_t)(span * a.n_out * esz));
+}
+
+// Decode one span of up to 64 ST pixels starting at pixel `first` (uv
+// already in uvs) and ending before end_px: footprint, staging, sampling,
+// MLP, store. The uv of the next span (next_first < 0: none) is requested
+// during this span, so that its latency overlaps the work of the span.
 template <class P, int HID, int NL, int ST, bool VEC4>
 __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, int64_t end_px, f32x4 *stage,
                                             const f32x4 *bias, f32x4 *ltab, const MfmaWeights<P, HID, NL> &W,
                                             SpanUv<ST> &uvs, int64_t next_first, int64_t next_end_px) {
   using Frag = typename P::Frag;
-  const int lane = threadIdx.x;
-  const int mode = a.lat.address;
-  const int n_levels = a.lat.n_levels;
-
   const int64_t left = end_px - first;
   const int span = left < 64 * ST ? (int)left : 64 * ST;
   const int span_salt = (int)first;
-  const int esz = a.out_f16 ? 2 : 4;
-  const __amdgpu_buffer_rsrc_t ors =
-      make_rsrc(reinterpret_cast<const char *>(a.out) + first * a.n_out * esz, (uint32_t)(span * a.n_out * esz));
+  const __amdgpu_buffer_rsrc_t ors = span_out(a, first, span);
 
   if (!NTC_UV_PREFETCH) uvs.load(a.uv, first, end_px);
   float u[ST], v[ST];
@@ -702,146 +894,8 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     u[q] = uvs.u[q];
     v[q] = uvs.v[q];
   }
-
-  bool staged = false;
   int kbw[kMaxLevels], kbase[kMaxLevels];
-  if (mode == 0) {
-    float umin = tap_coord(u[0]), umax = umin, vmin = tap_coord(v[0]), vmax = vmin;
-#pragma unroll
-    for (int q = 1; q < ST; ++q) {
-      umin = fminf(umin, tap_coord(u[q]));
-      umax = fmaxf(umax, tap_coord(u[q]));
-      vmin = fminf(vmin, tap_coord(v[q]));
-      vmax = fmaxf(vmax, tap_coord(v[q]));
-    }
-    umin = wave_min(umin);
-    umax = wave_max(umax);
-    vmin = wave_min(vmin);
-    vmax = wave_max(vmax);
-    // lane 4 k + s (k < 4): tap index of an extreme coordinate on level k,
-    // s = 0: left tap of umin, 1: left tap of umax, 2: top tap of vmin,
-    // 3: top tap of vmax
-    const int le = (lane >> 1) & 7;  // level le / 2, axis le % 2
-    const f32x4 tb = (ltab + opaque_zero(span_salt))[3 * (le >> 1) + (le & 1)];
-    const float ext = (lane & 2) ? ((lane & 1) ? vmax : vmin) : ((lane & 1) ? umax : umin);
-    const int ti = (int)tap_floor(ext, tb[0], tb[1], tb[2]);
-    // every lane of quad k receives the four values of level k
-    const int qbx = __builtin_amdgcn_mov_dpp(ti, 0x00, 0xF, 0xF, false);
-    const int qex = __builtin_amdgcn_mov_dpp(ti, 0x55, 0xF, 0xF, false);
-    const int qby = __builtin_amdgcn_mov_dpp(ti, 0xAA, 0xF, 0xF, false);
-    const int qey = __builtin_amdgcn_mov_dpp(ti, 0xFF, 0xF, 0xF, false);
-    // Staged region of level k: the whole blocks spanning texel columns
-    // [bx, ex + 1] (block columns col0 .. col0 + ncol - 1) on texel rows
-    // [by, ey + 1]. A staging item is one texel row of one block (4 texels);
-    // items are numbered level by level, row-major inside a level, and item
-    // t owns staged texels 4 t .. 4 t + 3, so level k starts at texel
-    // 4 ibase_k and its rows are 4 ncol_k texels wide.
-    const int qcol0 = qbx >> 2;
-    const int qncol = ((qex + 1) >> 2) - qcol0 + 1;
-    const int qnrow = qey - qby + 2;
-    const int qitems = (lane >> 2) < n_levels ? __mul24(qncol, qnrow) : 0;
-    int kitems[kMaxLevels], kib[kMaxLevels], total = 0;
-#pragma unroll
-    for (int k = 0; k < kMaxLevels; ++k) {
-      kitems[k] = __builtin_amdgcn_readlane(qitems, 4 * k);
-      const int col0 = __builtin_amdgcn_readlane(qcol0, 4 * k);
-      const int by = __builtin_amdgcn_readlane(qby, 4 * k);
-      kbw[k] = 4 * __builtin_amdgcn_readlane(qncol, 4 * k);
-      kib[k] = total;
-      // sampling: texel (i, j) of level k sits at j kbw + i + kbase
-      kbase[k] = 4 * total - by * kbw[k] - 4 * col0;
-      total += kitems[k];
-    }
-    if (4 * total <= a.stage_cap) {
-      staged = true;
-      // per-level staging records, written by the lead lane of each quad:
-      // {first item, blocks per staged row, 1 / that, first block column}
-      // and {first texel row, blocks per level row, block pointer}
-      f32x4 *srec = ltab + opaque_zero(span_salt) + LevelTab::kLevelEntries;
-      if ((lane & 3) == 0 && lane < 4 * kMaxLevels) {
-        const int k = lane >> 2;
-        const int ib = k == 0 ? kib[0] : (k == 1 ? kib[1] : (k == 2 ? kib[2] : kib[3]));
-        const f32x4 eb = (ltab + opaque_zero(span_salt))[3 * k + 2];
-        srec[2 * k] = (f32x4){__int_as_float(ib), __int_as_float(qncol), __builtin_amdgcn_rcpf((float)qncol),
-                              __int_as_float(qcol0)};
-        srec[2 * k + 1] = (f32x4){__int_as_float(qby), eb[2], eb[0], eb[1]};
-      }
-      // item t: its block row (blocks, index word) and staged texels; the
-      // row inside the level is (t - first + 1/2) / ncol rounded down, exact
-      // since the reciprocal's relative error (~2^-22) moves a quotient that
-      // is at least 1/(2 ncol) from an integer by < 1e-3 / ncol
-      auto item_fetch = [&](int t, int &Y) {
-        const int k = (t >= kib[1]) + (t >= kib[2]) + (t >= kib[3]);
-        const f32x4 r0 = srec[2 * k], r1 = srec[2 * k + 1];
-        const int tl = t - __float_as_int(r0[0]);
-        const int ncol = __float_as_int(r0[1]);
-        const int row = (int)(((float)tl + 0.5f) * r0[2]);
-        const int col = tl - __mul24(row, ncol);
-        Y = __float_as_int(r1[0]) + row;
-        const uint2 *blk =
-            (const uint2 *)(((unsigned long long)__float_as_uint(r1[3]) << 32) | __float_as_uint(r1[2]));
-        // footprint rows and blocks lie inside the level
-        return gload2u(blk + (__mul24(Y >> 2, __float_as_int(r1[1])) + __float_as_int(r0[3]) + col));
-      };
-      auto item_put = [&](int t, int Y, uint2 b) {
-        const uint32_t pos = (uint32_t)(Y & 3) << 2;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float3 val = texel_f32(bc1_numer(b.x, b.y, pos + i));
-          stage[4 * t + i] = (f32x4){val.x, val.y, val.z, 0.0f};
-        }
-      };
-      {
-        int Y = 0;
-        uint2 b = make_uint2(0u, 0u);
-        if (lane < total) b = item_fetch(lane, Y);
-        if (lane < total) item_put(lane, Y, b);
-      }
-      for (int t = lane + 64; t < total; t += 64) {
-        int Y;
-        const uint2 b = item_fetch(t, Y);
-        item_put(t, Y, b);
-      }
-    }
-  }
-  // Sub-spans of 64 pixels: every lane samples all levels of its pixel, the
-  // lane halves exchange operand halves, and the MLP runs on two N-tiles.
-  auto rotate = [&]() {
-#pragma unroll
-    for (int i = 0; i + 1 < ST; ++i) {
-      u[i] = u[i + 1];
-      v[i] = v[i + 1];
-    }
-  };
-  auto to_operands = [&](float (&xl)[8], float (&xh)[8], float uq, float vq, Frag (&bx)[2]) {
-    xl[6] = uq;
-    xl[7] = vq;
-    xh[6] = 0.0f;
-    xh[7] = 0.0f;
-    bx[0] = P::features(xl, W.in_scale);
-    bx[1] = P::features(xh, W.in_scale);
-    swap_halves<P>(bx[0], bx[1]);
-  };
-  auto put3 = [](float (&xl)[8], float (&xh)[8], int k, float3 c) {
-    float *x = k < 2 ? xl : xh;
-    const int o = 3 * (k & 1);
-    x[o] = c.x;
-    x[o + 1] = c.y;
-    x[o + 2] = c.z;
-  };
-  // MLP and store of sub-span q (`salt` varies from one call site and span
-  // to the next, see opaque_zero)
-  auto mlp = [&](const Frag (&bx)[2], int q, int salt) {
-    // both N-tiles in one MLP pass when the weights leave room for two sets
-    // of accumulators, otherwise one after the other
-    if constexpr (HID >= 64 && NL >= 3 && NTC_WIDE_NT == 1) {
-      const Frag b0[1] = {bx[0]}, b1[1] = {bx[1]};
-      mlp_store<P, HID, NL, 1, VEC4>(a, W, bias, ors, b0, 2 * q, salt);
-      mlp_store<P, HID, NL, 1, VEC4>(a, W, bias, ors, b1, 2 * q + 1, salt + 1);
-    } else {
-      mlp_store<P, HID, NL, 2, VEC4>(a, W, bias, ors, bx, 2 * q, salt);
-    }
-  };
+  const bool staged = stage_span<ST>(a, u, v, stage, ltab, ltab + LevelTab::kLevelEntries, span_salt, kbw, kbase);
 
   if (staged) {
     // The next span's uv is requested only now: the vector-memory counter
@@ -853,55 +907,26 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     if (NTC_UV_PREFETCH && next_first >= 0) uvs.load(a.uv, next_first, next_end_px);
     NTC_UNROLL_STAGED
     for (int q = 0; q < ST; ++q) {
-      float xl[8], xh[8];
-      const float uq = u[0], vq = v[0];
-      rotate();
-#pragma unroll
-      for (int k = 0; k < kMaxLevels; ++k) {
-        float3 c = make_float3(0.f, 0.f, 0.f);
-        if (k < n_levels) {
-          TabLevel Lk;
-          Lk.read(ltab + opaque_zero(span_salt + q), k);
-          int i0, j0;
-          float fx, fy;
-          clamp_tap(tap_coord(uq), Lk.fw, Lk.cx, Lk.wm2, i0, fx);
-          clamp_tap(tap_coord(vq), Lk.fh, Lk.cy, Lk.hm2, j0, fy);
-          // taps lie inside the staged region of the level
-          const int r = __mul24(j0, kbw[k]) + i0 + kbase[k];
-          const f32x4 t00 = stage[r], t10 = stage[r + 1], t01 = stage[r + kbw[k]], t11 = stage[r + kbw[k] + 1];
-          c = blend4(make_float3(t00[0], t00[1], t00[2]), make_float3(t10[0], t10[1], t10[2]),
-                     make_float3(t01[0], t01[1], t01[2]), make_float3(t11[0], t11[1], t11[2]), fx, fy);
-        }
-        put3(xl, xh, k, c);
-      }
       Frag bx[2];
-      to_operands(xl, xh, uq, vq, bx);
-      mlp(bx, q, span_salt + 2 * q);
+      staged_operands<P>(a, stage, ltab, kbw, kbase, u[q], v[q], W.in_scale, span_salt + q, bx);
+      subspan_mlp<P, HID, NL, VEC4>(a, W, bias, ors, bx, q, span_salt + 2 * q);
     }
     return;
   }
 
-  // Direct block fetches (footprint beyond the LDS region, or wrap
-  // addressing); one sub-span at a time.
+  // direct block fetches; one sub-span at a time
 #pragma unroll 1
   for (int q = 0; q < ST; ++q) {
     if (64 * q >= span) break;
-    float xl[8], xh[8];
     const float uq = u[0], vq = v[0];
-    rotate();
 #pragma unroll
-    for (int k = 0; k < kMaxLevels; ++k) {
-      float3 c = make_float3(0.f, 0.f, 0.f);
-      if (k < n_levels) {
-        TabLevel Lk;
-        Lk.read(ltab + opaque_zero(q), k);
-        c = sample_direct_t(Lk, uq, vq, mode);
-      }
-      put3(xl, xh, k, c);
+    for (int i = 0; i + 1 < ST; ++i) {
+      u[i] = u[i + 1];
+      v[i] = v[i + 1];
     }
     Frag bx[2];
-    to_operands(xl, xh, uq, vq, bx);
-    mlp(bx, q, 2 * q);
+    direct_operands<P>(a, ltab, uq, vq, W.in_scale, q, bx);
+    subspan_mlp<P, HID, NL, VEC4>(a, W, bias, ors, bx, q, 2 * q);
   }
   // the next span's uv, completed here: this path then leaves no pending
   // load behind and the wait state where the paths join is the staged one
