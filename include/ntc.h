@@ -128,6 +128,14 @@ ntc_status ntc_mlp_pack_size(const ntc_mlp *mlp, int32_t compute, size_t *bytes)
 /* Write the packed weight image used by ntc_decode: weights converted to
  * `compute`, padded to the matrix-core tile shapes and reordered so that
  * consecutive layers chain in registers; biases kept in FP32.
+ * For NTC_F16, hidden neuron i of layer l is stored scaled by 2^-e(l, i),
+ * e >= 0 chosen from an interval bound so that its pre-activation is at
+ * most 1 whenever the latent values and u, v lie in [0, 1] (the weights
+ * and biases absorb the powers of two, so the network is unchanged); the
+ * decode then applies ReLU as the [0, 1] clamp of the FP16 conversion on
+ * spans whose coordinates lie in the unit square, and the max-based ReLU
+ * elsewhere. If a bound exceeds 2^10 the image is left unscaled and every
+ * span uses the max-based ReLU.
  * For NTC_FP8_E4M3, per-layer scales s_w = 448 / max|W_l| are computed on
  * the device and act_amax [device, n_layers floats] must hold the largest
  * |input| of every layer (see ntc_calibrate_fp8); s_a = 448 / act_amax[l].

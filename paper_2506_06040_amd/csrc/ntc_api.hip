@@ -161,7 +161,7 @@ const char *ntc_status_string(ntc_status s) {
 
 const char *ntc_last_error(void) { return g_err; }
 
-int32_t ntc_version(void) { return 10000 * 0 + 100 * 3 + 0; }
+int32_t ntc_version(void) { return 10000 * 0 + 100 * 4 + 0; }
 
 ntc_status ntc_mlp_pack_size(const ntc_mlp *mlp, int32_t compute, size_t *bytes) {
   if (!bytes) return fail(NTC_E_NULL, "bytes is NULL");

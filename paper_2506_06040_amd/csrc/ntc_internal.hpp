@@ -35,7 +35,8 @@ struct PackLayout {
   size_t total;
   uint32_t w_off[kMaxLayers];     // bytes
   uint32_t b_off[kMaxLayers];     // bytes
-  uint32_t scale_off;             // bytes (FP8 only)
+  uint32_t scale_off;             // bytes (FP8 scales; FP16 ReLU-by-clamp flag)
+  uint32_t exp_off;               // bytes (FP16: per-neuron scale exponents)
   int32_t mt[kMaxLayers];         // M-tiles (32 rows) per layer
   int32_t kc[kMaxLayers];         // K-steps per layer
   int32_t frag_elems;             // operand elements per lane (8 FP16, 32 E4M3)

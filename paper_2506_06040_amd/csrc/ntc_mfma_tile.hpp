@@ -94,6 +94,15 @@ __device__ __forceinline__ half2_t relu_pk(float a, float b) {
   return __builtin_elementwise_max(h, z);
 }
 
+// ReLU for activations known to be at most 1: the [0, 1] clamp, which the
+// compiler folds into the conversion (v_cvt_pk_f16_f32 with the clamp bit).
+__device__ __forceinline__ half2_t relu_unit_pk(float a, float b) {
+  const f32x2 v = {a, b};
+  const half2_t h = __builtin_convertvector(v, half2_t);
+  const half2_t z = {(_Float16)0.0f, (_Float16)0.0f}, o = {(_Float16)1.0f, (_Float16)1.0f};
+  return __builtin_elementwise_min(__builtin_elementwise_max(h, z), o);
+}
+
 // FP16 operands, 32x32x16 tiles: a K-step is 16 inputs, 8 halves per lane.
 struct PrecF16 {
   using Frag = half8_t;
@@ -115,8 +124,9 @@ struct PrecF16 {
     return f;
   }
   // K-step c of the next layer = ReLU of accumulator rows 8 (c % 2) .. + 7
-  // of M-tile c / 2.
-  template <int MT, int KS>
+  // of M-tile c / 2. UNIT: the activations are at most 1 (scaled image,
+  // coordinates inside the unit square), so ReLU is the [0, 1] clamp.
+  template <int MT, int KS, bool UNIT>
   __device__ __forceinline__ static void next_operands(const f32x16 (&acc)[MT], Frag (&hb)[KS], float) {
 #pragma unroll
     for (int c = 0; c < KS; ++c) {
@@ -124,7 +134,7 @@ struct PrecF16 {
       const int o = 8 * (c & 1);
 #pragma unroll
       for (int i = 0; i < 8; i += 2) {
-        const half2_t h = relu_pk(v[o + i], v[o + i + 1]);
+        const half2_t h = UNIT ? relu_unit_pk(v[o + i], v[o + i + 1]) : relu_pk(v[o + i], v[o + i + 1]);
         hb[c][i] = h[0];
         hb[c][i + 1] = h[1];
       }
@@ -169,7 +179,7 @@ struct PrecF8 {
   }
   // K-step c of the next layer: bytes 0..15 from all rows of M-tile 2c,
   // bytes 16..31 from M-tile 2c + 1 (zero when it does not exist).
-  template <int MT, int KS>
+  template <int MT, int KS, bool>
   __device__ __forceinline__ static void next_operands(const f32x16 (&acc)[MT], Frag (&hb)[KS], float s) {
 #pragma unroll
     for (int c = 0; c < KS; ++c) {
@@ -279,6 +289,8 @@ struct MfmaWeights {
   Frag wo[KS];
   float epi[kMaxLayers];
   float in_scale;
+  float unit_flag;  // FP16 image scaled for ReLU by clamp (1.0) or not (0.0), as loaded
+  int unit_relu;    // the same, wave-uniform (set by ready())
 
   __device__ __forceinline__ void load(const uint8_t *packed, const PackLayout &lay, int lane) {
     const Frag *f = reinterpret_cast<const Frag *>(packed + lay.w_off[0]);
@@ -296,8 +308,11 @@ struct MfmaWeights {
 #pragma unroll
     for (int c = 0; c < KS; ++c) wo[c] = gload(fo + c * 64 + lane);
     in_scale = 1.0f;
+    unit_flag = 0.0f;
+    unit_relu = 0;
 #pragma unroll
     for (int l = 0; l < kMaxLayers; ++l) epi[l] = 1.0f;
+    if (!P::kScaled) unit_flag = gload(reinterpret_cast<const float *>(packed + lay.scale_off));
     if (P::kScaled) {
       const float *sc = reinterpret_cast<const float *>(packed + lay.scale_off);
       in_scale = gload(sc);
@@ -309,7 +324,7 @@ struct MfmaWeights {
   // persistent loop entered with these loads still pending would carry that
   // state into its body and wait for the whole vector-memory counter there
   // on every iteration.
-  __device__ __forceinline__ void ready() const {
+  __device__ __forceinline__ void ready() {
 #if defined(__HIP_DEVICE_COMPILE__)  // the constraints exist for the GPU target only
 #pragma unroll
     for (int m = 0; m < MT; ++m) asm volatile("" ::"v"(w0[m]));
@@ -324,7 +339,9 @@ struct MfmaWeights {
 #pragma unroll
     for (int l = 0; l < kMaxLayers; ++l) asm volatile("" ::"v"(epi[l]));
     asm volatile("" ::"v"(in_scale));
+    asm volatile("" ::"v"(unit_flag));
 #endif
+    unit_relu = __builtin_amdgcn_readfirstlane(unit_flag != 0.0f ? 1 : 0);
   }
 };
 
@@ -404,7 +421,7 @@ struct BiasLds {
 
 // MLP over NT N-tiles of 32 pixels (N-tiles t0 .. t0 + NT - 1 of the span) and
 // store. VEC4: the output width is a multiple of 4.
-template <class P, int HID, int NL, int NT>
+template <class P, int HID, int NL, int NT, bool UNIT>
 __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, const f32x4 *bias,
                                             const typename P::Frag (&bx)[NT], f32x16 (&z)[NT], int salt) {
   using BL = BiasLds<HID, NL>;
@@ -427,7 +444,7 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
   for (int k = 0; k < NH; ++k) {
     Frag hb[NT][KS];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) P::template next_operands<MT, KS>(acc[t], hb[t], W.epi[k]);
+    for (int t = 0; t < NT; ++t) P::template next_operands<MT, KS, UNIT>(acc[t], hb[t], W.epi[k]);
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
       const f32x16 bm = BL::get(bias, BL::off(1 + k, m), h);
@@ -442,7 +459,7 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
   }
   Frag hb[NT][KS];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) P::template next_operands<MT, KS>(acc[t], hb[t], W.epi[NL - 2]);
+  for (int t = 0; t < NT; ++t) P::template next_operands<MT, KS, UNIT>(acc[t], hb[t], W.epi[NL - 2]);
   const f32x16 bo = BL::get(bias, BL::off_out(), h);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -516,12 +533,12 @@ __device__ __forceinline__ void store_outputs(const DecodeArgs &a, float out_sca
 
 // MLP over NT N-tiles of 32 pixels (N-tiles t0 .. t0 + NT - 1 of the span) and
 // store.
-template <class P, int HID, int NL, int NT, bool VEC4>
+template <class P, int HID, int NL, int NT, bool VEC4, bool UNIT>
 __device__ __forceinline__ void mlp_store(const DecodeArgs &a, const MfmaWeights<P, HID, NL> &W,
                                           const f32x4 *bias, __amdgpu_buffer_rsrc_t ors,
                                           const typename P::Frag (&bx)[NT], int t0, int salt) {
   f32x16 z[NT];
-  mlp_compute<P, HID, NL, NT>(W, bias, bx, z, salt);
+  mlp_compute<P, HID, NL, NT, UNIT>(W, bias, bx, z, salt);
   store_outputs<P, NT, VEC4>(a, P::kScaled ? W.epi[NL - 1] : 1.0f, ors, z, t0);
 }
 
@@ -675,13 +692,15 @@ __device__ __forceinline__ void swap_halves(typename P::Frag &lo, typename P::Fr
 // the function returns true with kbw / kbase locating texel (i, j) of level
 // k at j kbw[k] + i + kbase[k]. `srec` is this wave's staging record area
 // (2 entries per level), `salt` a value that changes from span to span (see
-// opaque_zero).
+// opaque_zero). in_unit (set when the span is staged): every u and v of the
+// span lies in [0, 1] (NaN and infinities do not).
 template <int ST>
 __device__ __forceinline__ bool stage_span(const DecodeArgs &a, const float (&u)[ST], const float (&v)[ST],
                                            f32x4 *stage, const f32x4 *ltab, f32x4 *srec, int salt,
-                                           int (&kbw)[kMaxLevels], int (&kbase)[kMaxLevels]) {
+                                           int (&kbw)[kMaxLevels], int (&kbase)[kMaxLevels], bool &in_unit) {
   const int lane = threadIdx.x & 63;
   const int n_levels = a.lat.n_levels;
+  in_unit = false;
   if (a.lat.address != 0) return false;
   float umin = tap_coord(u[0]), umax = umin, vmin = tap_coord(v[0]), vmax = vmin;
 #pragma unroll
@@ -695,6 +714,8 @@ __device__ __forceinline__ bool stage_span(const DecodeArgs &a, const float (&u)
   umax = wave_max(umax);
   vmin = wave_min(vmin);
   vmax = wave_max(vmax);
+  // the sanitised extremes: NaN became -2^20, infinities +-2^20
+  in_unit = umin >= 0.0f && umax <= 1.0f && vmin >= 0.0f && vmax <= 1.0f;
   // lane 4 k + s (k < 4): tap index of an extreme coordinate on level k,
   // s = 0: left tap of umin, 1: left tap of umax, 2: top tap of vmin,
   // 3: top tap of vmax
@@ -850,8 +871,9 @@ __device__ __forceinline__ void direct_operands(const DecodeArgs &a, const f32x4
   pixel_operands<P>(xl, xh, uq, vq, in_scale, bx);
 }
 
-// MLP and store of sub-span q of a span (two N-tiles of 32 pixels).
-template <class P, int HID, int NL, bool VEC4>
+// MLP and store of sub-span q of a span (two N-tiles of 32 pixels). UNIT:
+// ReLU by the [0, 1] clamp (see PrecF16::next_operands).
+template <class P, int HID, int NL, bool VEC4, bool UNIT>
 __device__ __forceinline__ void subspan_mlp(const DecodeArgs &a, const MfmaWeights<P, HID, NL> &W, const f32x4 *bias,
                                             __amdgpu_buffer_rsrc_t ors, const typename P::Frag (&bx)[2], int q,
                                             int salt) {
@@ -860,10 +882,10 @@ __device__ __forceinline__ void subspan_mlp(const DecodeArgs &a, const MfmaWeigh
   // accumulators, otherwise one after the other
   if constexpr (HID >= 64 && NL >= 3 && NTC_WIDE_NT == 1) {
     const Frag b0[1] = {bx[0]}, b1[1] = {bx[1]};
-    mlp_store<P, HID, NL, 1, VEC4>(a, W, bias, ors, b0, 2 * q, salt);
-    mlp_store<P, HID, NL, 1, VEC4>(a, W, bias, ors, b1, 2 * q + 1, salt + 1);
+    mlp_store<P, HID, NL, 1, VEC4, UNIT>(a, W, bias, ors, b0, 2 * q, salt);
+    mlp_store<P, HID, NL, 1, VEC4, UNIT>(a, W, bias, ors, b1, 2 * q + 1, salt + 1);
   } else {
-    mlp_store<P, HID, NL, 2, VEC4>(a, W, bias, ors, bx, 2 * q, salt);
+    mlp_store<P, HID, NL, 2, VEC4, UNIT>(a, W, bias, ors, bx, 2 * q, salt);
   }
 }
 
@@ -895,9 +917,15 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     v[q] = uvs.v[q];
   }
   int kbw[kMaxLevels], kbase[kMaxLevels];
-  const bool staged = stage_span<ST>(a, u, v, stage, ltab, ltab + LevelTab::kLevelEntries, span_salt, kbw, kbase);
+  bool in_unit;
+  const bool staged =
+      stage_span<ST>(a, u, v, stage, ltab, ltab + LevelTab::kLevelEntries, span_salt, kbw, kbase, in_unit);
 
-  if (staged) {
+  // FP16: the staged path runs with ReLU by clamp, so it takes only spans
+  // whose activations are known to be at most 1 (image scaled for it,
+  // coordinates in the unit square); other spans take the direct path with
+  // the max-based ReLU
+  if (staged && (P::kScaled || (in_unit && W.unit_relu != 0))) {
     // The next span's uv is requested only now: the vector-memory counter
     // completes in order, so a load issued before the staging fetches would be
     // waited for together with them. After it come exactly the stores of the
@@ -909,7 +937,7 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     for (int q = 0; q < ST; ++q) {
       Frag bx[2];
       staged_operands<P>(a, stage, ltab, kbw, kbase, u[q], v[q], W.in_scale, span_salt + q, bx);
-      subspan_mlp<P, HID, NL, VEC4>(a, W, bias, ors, bx, q, span_salt + 2 * q);
+      subspan_mlp<P, HID, NL, VEC4, !P::kScaled>(a, W, bias, ors, bx, q, span_salt + 2 * q);
     }
     return;
   }
@@ -926,7 +954,7 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     }
     Frag bx[2];
     direct_operands<P>(a, ltab, uq, vq, W.in_scale, q, bx);
-    subspan_mlp<P, HID, NL, VEC4>(a, W, bias, ors, bx, q, 2 * q);
+    subspan_mlp<P, HID, NL, VEC4, false>(a, W, bias, ors, bx, q, 2 * q);
   }
   // the next span's uv, completed here: this path then leaves no pending
   // load behind and the wait state where the paths join is the staged one

@@ -51,6 +51,8 @@ PackLayout pack_layout(const MlpShape &s, int compute) {
   }
   L.scale_off = align_up(off, 256);
   off = L.scale_off + 4 * kMaxLayers * sizeof(float);
+  L.exp_off = align_up(off, 256);
+  off = L.exp_off + kMaxLayers * 64 * sizeof(int32_t);
   L.total = align_up(off, 256);
   return L;
 }
@@ -129,6 +131,66 @@ __global__ void pack_scales_kernel(PackArgs a) {
   }
 }
 
+// FP16 image: per-neuron power-of-two scales that let the matrix-core decode
+// apply ReLU and the FP16 conversion in one instruction (conversion with
+// the [0, 1] clamp). Hidden neuron i of layer l is stored as its activation
+// times 2^-e(l, i), with e chosen so that the scaled pre-activation cannot
+// exceed 1 when every input lies in [0, 1] (BC1 latent values always do;
+// the coordinate features do when u, v are in [0, 1]): an interval bound
+// over that box, with inputs of hidden layers in [0, 2^e] of the previous
+// layer, plus a margin for FP16 products and FP32 sums (2^-8 of the
+// absolute sum, far above their rounding). The weights of layer l are then
+// W(i, j) 2^(e(l-1, j) - e(l, i)) and its bias b(i) 2^-e(l, i) (e = 0 for
+// the network inputs and outputs): powers of two, so the network computes
+// the same function and only the placement of FP16 rounding in the
+// subnormal range changes. When a bound exceeds 2^kMaxClampExp the image
+// keeps e = 0 everywhere and the flag (first scale word) is 0, which sends
+// every span to the max-based ReLU.
+constexpr int kMaxClampExp = 10;
+
+__device__ __forceinline__ int bound_exp(double u) {
+  if (!(u > 1.0)) return u == u ? 0 : kMaxClampExp + 1;
+  int k;
+  const double m = frexp(u, &k);  // u = m 2^k, m in [0.5, 1)
+  return m == 0.5 ? k - 1 : k;
+}
+
+__global__ __launch_bounds__(64) void pack_bounds_kernel(PackArgs a) {
+  __shared__ int e_prev[64];
+  __shared__ int bad;
+  const int i = threadIdx.x;
+  const int Ln = a.s.n_layers;
+  int *ex = reinterpret_cast<int *>(a.packed + a.lay.exp_off);
+  e_prev[i] = 0;
+  if (i == 0) bad = 0;
+  __syncthreads();
+  for (int l = 0; l + 1 < Ln; ++l) {
+    const int rows = a.p.dims[l + 1], cols = a.p.dims[l];
+    int e = 0;
+    if (i < rows) {
+      const double b = a.p.b[l][i];
+      double hi = b, mag = fabs(b);
+      for (int j = 0; j < cols; ++j) {
+        const double w = a.p.W[l][(int64_t)i * cols + j];
+        const double x = ldexp(1.0, e_prev[j]);
+        if (w > 0.0) hi += w * x;
+        mag += fabs(w) * x;
+      }
+      e = bound_exp(hi + ldexp(mag, -8) + ldexp(1.0, -20));
+      if (e > kMaxClampExp) bad = 1;
+    }
+    __syncthreads();
+    e_prev[i] = e;
+    ex[l * 64 + i] = e;
+    __syncthreads();
+  }
+  const bool ok = bad == 0;
+  for (int l = Ln - 1; l < kMaxLayers; ++l) ex[l * 64 + i] = 0;
+  if (!ok)
+    for (int l = 0; l + 1 < Ln; ++l) ex[l * 64 + i] = 0;
+  if (i == 0) reinterpret_cast<float *>(a.packed + a.lay.scale_off)[0] = ok ? 1.0f : 0.0f;
+}
+
 __device__ __forceinline__ uint8_t to_e4m3(float v) {
   v = fminf(fmaxf(v, -448.0f), 448.0f);
   return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xFF);
@@ -185,7 +247,10 @@ __global__ void pack_kernel(PackArgs a, int64_t n_w_elems, int64_t n_elems) {
         if (f8) {
           (a.packed + L.w_off[l])[r] = to_e4m3(v * sc[3 * l + 2]);
         } else {
-          ((_Float16 *)(a.packed + L.w_off[l]))[r] = (_Float16)v;
+          const int *ex = (const int *)(a.packed + L.exp_off);
+          const int e_in = (l > 0 && col >= 0) ? ex[(l - 1) * 64 + col] : 0;
+          const int e_out = (l + 1 < Ln && row < 64) ? ex[l * 64 + row] : 0;
+          ((_Float16 *)(a.packed + L.w_off[l]))[r] = (_Float16)ldexpf(v, e_in - e_out);
         }
         return;
       }
@@ -203,6 +268,7 @@ __global__ void pack_kernel(PackArgs a, int64_t n_w_elems, int64_t n_elems) {
       const int rows = a.p.dims[l + 1];
       float v = row < rows ? a.p.b[l][row] : 0.f;
       if (a.compute == 3) v = v * (sc[3 * l + 2] * sc[3 * l + 0]);
+      if (a.compute == 1 && l + 1 < Ln) v = ldexpf(v, -((const int *)(a.packed + L.exp_off))[l * 64 + row]);
       ((float *)(a.packed + L.b_off[l]))[r] = v;
       return;
     }
@@ -228,8 +294,11 @@ hipError_t launch_pack(const MlpShape &s, const MlpPtrs &p, int compute, const f
     n_all = n_w;
     for (int l = 0; l < s.n_layers; ++l) n_all += (int64_t)lay.mt[l] * 32;
   }
-  if (compute == 3) {
-    hipLaunchKernelGGL(pack_scales_kernel, dim3(s.n_layers), dim3(256), 0, st, a);
+  if (compute == 3 || compute == 1) {
+    if (compute == 3)
+      hipLaunchKernelGGL(pack_scales_kernel, dim3(s.n_layers), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL(pack_bounds_kernel, dim3(1), dim3(64), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -150,6 +150,69 @@ def test_staged_equals_direct_and_deterministic():
         assert torch.equal(a[:4099], f)
 
 
+def _white_pyramid(sizes):
+    """BC1 levels whose every texel is (1, 1, 1): both endpoints 0xFFFF."""
+    return [np.full((h // 4, w // 4), 0xFFFFFFFF, np.uint64) for (w, h) in sizes]
+
+
+def test_f16_unit_relu_at_its_bound():
+    """FP16 images scale hidden neuron i of layer l by 2^-e(l, i) so that ReLU
+    is the conversion's [0, 1] clamp. Here layer 1 reaches its interval bound:
+    positive weights, white latents and u = v = 1 make every input 1, and
+    each row sums to just below a power of two, so a scale one binade too
+    small would saturate. Parity with the oracle, and the staged path (clamp)
+    equals the direct path (max) bit for bit."""
+    ntc = _ntc()
+    rng = np.random.default_rng(31)
+    sizes = [(64, 64), (32, 32), (16, 16), (8, 8)]
+    lat_np = _white_pyramid(sizes)
+    W1 = rng.random((64, 14))
+    W1 /= W1.sum(1, keepdims=True)
+    c = rng.uniform(1.5, 1.98, 64) * 2.0 ** rng.integers(-2, 3, 64)
+    Ws = [(W1 * (0.9 * c)[:, None]).astype(np.float32), (rng.random((64, 64)) * 0.05).astype(np.float32),
+          (rng.random((64, 64)) * 0.05).astype(np.float32), I.xavier_mlp(rng, (64, 8))[0][0]]
+    bs = [(0.1 * c).astype(np.float32), np.full(64, 0.01, np.float32), np.full(64, 0.01, np.float32),
+          np.zeros(8, np.float32)]
+    n = 4096
+    uv = (1.0 - rng.random((n, 2)) / 8).astype(np.float32)
+    uv[::7] = 1.0
+    lat, mlp = _gpu_case(lat_np, Ws, bs, I.PAPER_SHIFT)
+    uvt = torch.from_numpy(uv).cuda()
+    packed = ntc.pack(mlp, "f16")
+    out = ntc.decode(lat, mlp, uvt, compute="f16", packed=packed)
+    # 64 texels of staging cannot hold these footprints: every span direct
+    direct = ntc.decode(lat, mlp, uvt, compute="f16", packed=packed, cfg=ntc.tile_cfg(stage_capacity=64))
+    olat, omlp = _oracle_case(lat_np, Ws, bs, I.PAPER_SHIFT)
+    ref = O.decode(olat, omlp, uv)
+    err = _report("unit relu at bound", out.cpu().numpy(), ref)
+    assert np.all(err <= TOL_F16_ABS)
+    assert torch.equal(out, direct)
+
+
+def test_f16_large_bounds_parity():
+    """A neuron whose interval bound exceeds 2^10 (bias 3000 on one layer-2
+    neuron, whose outgoing weights are zero) leaves the FP16 image unscaled,
+    with max-based ReLU everywhere: parity with the oracle, and the staged and
+    direct paths agree bit for bit."""
+    ntc = _ntc()
+    rng = np.random.default_rng(32)
+    lat_np = I.bc1_pyramid(rng, [(64, 64), (32, 32), (16, 16), (8, 8)])
+    Ws, bs = I.xavier_mlp(rng, (14, 64, 64, 64, 8), bias="normal")
+    bs[1][5] = 3000.0
+    Ws[2][:, 5] = 0.0
+    uv = I.pixel_uv(64, 48)
+    lat, mlp = _gpu_case(lat_np, Ws, bs, I.PAPER_SHIFT)
+    uvt = torch.from_numpy(uv).cuda()
+    packed = ntc.pack(mlp, "f16")
+    out = ntc.decode(lat, mlp, uvt, compute="f16", packed=packed)
+    direct = ntc.decode(lat, mlp, uvt, compute="f16", packed=packed, cfg=ntc.tile_cfg(stage_capacity=64))
+    olat, omlp = _oracle_case(lat_np, Ws, bs, I.PAPER_SHIFT)
+    ref = O.decode(olat, omlp, uv)
+    err = _report("large bounds f16", out.cpu().numpy(), ref)
+    assert np.all(err <= TOL_F16_ABS)
+    assert torch.equal(out, direct)
+
+
 def test_random_uv_fallback_parity():
     """Random uv: tile footprints exceed the staging capacity -> direct fetches."""
     ntc = _ntc()
