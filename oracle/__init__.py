@@ -214,11 +214,15 @@ def layer_amax(lat: Latents, mlp: Mlp, uv: np.ndarray) -> np.ndarray:
     return amax
 
 
-def fp8_scales(Ws, amax_act):
-    """Per-layer E4M3 scales: s = 448 / max|.| computed in float32, as float64 values."""
+def fp8_scales(Ws, amax_act, pow2: bool = False):
+    """Per-layer E4M3 scales: s = 448 / max|.| computed in float32, as float64
+    values; with pow2, the largest power of two not above that quotient."""
     w_scale = np.array([np.float32(448.0) / np.float32(np.max(np.abs(np.asarray(w, np.float32))))
                         for w in Ws], dtype=np.float64)
     a_scale = np.array([np.float32(448.0) / np.float32(a) for a in amax_act], dtype=np.float64)
+    if pow2:
+        w_scale = np.ldexp(1.0, np.frexp(w_scale)[1] - 1)
+        a_scale = np.ldexp(1.0, np.frexp(a_scale)[1] - 1)
     return w_scale, a_scale
 
 

@@ -109,7 +109,7 @@ struct PrecF16 {
   static constexpr int KSTEP = 16;
   static constexpr bool kScaled = false;
   static constexpr int kFeatDwords = 4;  // dwords of a fragment that carry features
-  __device__ __forceinline__ static f32x16 mma(Frag a, Frag b, f32x16 c) {
+  __device__ __forceinline__ static f32x16 mma(Frag a, Frag b, f32x16 c, int, const int (&)[2]) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
   }
   __device__ __forceinline__ static Frag features(const float (&x)[8], float) {
@@ -167,9 +167,19 @@ struct PrecF8 {
   static constexpr int KSTEP = 64;
   static constexpr bool kScaled = true;
   static constexpr int kFeatDwords = 2;
-  __device__ __forceinline__ static f32x16 mma(Frag a, Frag b, f32x16 c) {
-    // format 0 = E4M3 for both operands; E8M0 scale 127 = 2^0
-    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+  // Format 0 = E4M3 for both operands. The weights' E8M0 block scale
+  // (127 + p for 2^p) carries layer l's epilogue factor: byte l % 4 of
+  // sc[l / 4]; the activations' is 127 = 2^0, byte 1 of sc[1]. (The scale
+  // operands are vector registers; the byte is chosen by op_sel.) l is a
+  // constant after unrolling.
+  __device__ __forceinline__ static f32x16 mma(Frag a, Frag b, f32x16 c, int l, const int (&sc)[2]) {
+    switch (l) {
+      case 0: return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, sc[0], 1, sc[1]);
+      case 1: return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 1, sc[0], 1, sc[1]);
+      case 2: return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 2, sc[0], 1, sc[1]);
+      case 3: return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 3, sc[0], 1, sc[1]);
+      default: return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, sc[1], 1, sc[1]);
+    }
   }
   __device__ __forceinline__ static Frag features(const float (&x)[8], float s) {
     Frag f = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -178,9 +188,12 @@ struct PrecF8 {
     return f;
   }
   // K-step c of the next layer: bytes 0..15 from all rows of M-tile 2c,
-  // bytes 16..31 from M-tile 2c + 1 (zero when it does not exist).
+  // bytes 16..31 from M-tile 2c + 1 (zero when it does not exist). The
+  // accumulators are already in the next layer's input scale (the layer's
+  // matrix instructions applied it), so this is ReLU, saturation and the
+  // conversion.
   template <int MT, int KS, bool>
-  __device__ __forceinline__ static void next_operands(const f32x16 (&acc)[MT], Frag (&hb)[KS], float s) {
+  __device__ __forceinline__ static void next_operands(const f32x16 (&acc)[MT], Frag (&hb)[KS], float) {
 #pragma unroll
     for (int c = 0; c < KS; ++c) {
 #pragma unroll
@@ -189,7 +202,7 @@ struct PrecF8 {
           const f32x16 &v = acc[2 * c + q];
 #pragma unroll
           for (int w = 0; w < 4; ++w)
-            hb[c][4 * q + w] = pack4_relu_e4m3(v[4 * w] * s, v[4 * w + 1] * s, v[4 * w + 2] * s, v[4 * w + 3] * s);
+            hb[c][4 * q + w] = pack4_relu_e4m3(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
         } else {
 #pragma unroll
           for (int w = 0; w < 4; ++w) hb[c][4 * q + w] = 0;
@@ -287,7 +300,8 @@ struct MfmaWeights {
   Frag w0[MT];
   Frag wh[NH][MT][KS];
   Frag wo[KS];
-  float epi[kMaxLayers];
+  float epi[kMaxLayers];  // E4M3: epilogue factor of each layer (a power of two), as loaded
+  int escale[2];          // the same as E8M0 bytes (see PrecF8::mma; set by ready())
   float in_scale;
   float unit_flag;  // FP16 image scaled for ReLU by clamp (1.0) or not (0.0), as loaded
   int unit_relu;    // the same, wave-uniform (set by ready())
@@ -342,6 +356,12 @@ struct MfmaWeights {
     asm volatile("" ::"v"(unit_flag));
 #endif
     unit_relu = __builtin_amdgcn_readfirstlane(unit_flag != 0.0f ? 1 : 0);
+    // 2^p = 0.5 * 2^(p + 1): frexp's exponent is p + 1
+    int e[kMaxLayers];
+#pragma unroll
+    for (int l = 0; l < kMaxLayers; ++l) e[l] = P::kScaled ? 126 + __builtin_amdgcn_frexp_expf(epi[l]) : 127;
+    escale[0] = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
+    escale[1] = e[4] | (127 << 8);
   }
 };
 
@@ -438,7 +458,7 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
   for (int m = 0; m < MT; ++m) {
     const f32x16 bm = BL::get(bias, BL::off(0, m), h);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t][m] = P::mma(W.w0[m], bx[t], bm);
+    for (int t = 0; t < NT; ++t) acc[t][m] = P::mma(W.w0[m], bx[t], bm, 0, W.escale);
   }
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
@@ -450,9 +470,9 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
       const f32x16 bm = BL::get(bias, BL::off(1 + k, m), h);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        f32x16 s = P::mma(W.wh[k][m][0], hb[t][0], bm);
+        f32x16 s = P::mma(W.wh[k][m][0], hb[t][0], bm, 1 + k, W.escale);
 #pragma unroll
-        for (int c = 1; c < KS; ++c) s = P::mma(W.wh[k][m][c], hb[t][c], s);
+        for (int c = 1; c < KS; ++c) s = P::mma(W.wh[k][m][c], hb[t][c], s, 1 + k, W.escale);
         acc[t][m] = s;
       }
     }
@@ -463,9 +483,9 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
   const f32x16 bo = BL::get(bias, BL::off_out(), h);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    f32x16 s = P::mma(W.wo[0], hb[t][0], bo);
+    f32x16 s = P::mma(W.wo[0], hb[t][0], bo, NL - 1, W.escale);
 #pragma unroll
-    for (int c = 1; c < KS; ++c) s = P::mma(W.wo[c], hb[t][c], s);
+    for (int c = 1; c < KS; ++c) s = P::mma(W.wo[c], hb[t][c], s, NL - 1, W.escale);
     z[t] = s;
   }
 }
@@ -473,7 +493,7 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
 // Sigmoid of the output pre-activations of NT N-tiles (N-tiles t0 .. t0 +
 // NT - 1 of the span) and store. VEC4: the output width is a multiple of 4.
 template <class P, int NT, bool VEC4>
-__device__ __forceinline__ void store_outputs(const DecodeArgs &a, float out_scale, __amdgpu_buffer_rsrc_t ors,
+__device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buffer_rsrc_t ors,
                                               const f32x16 (&z)[NT], int t0) {
   const int lane = (threadIdx.x & 63);
   const int h = lane >> 5;
@@ -496,7 +516,7 @@ __device__ __forceinline__ void store_outputs(const DecodeArgs &a, float out_sca
         if (j > 0) asm volatile("" : "+v"(zj));
         f32x4 f;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) f[i] = sigmoid_fast(P::kScaled ? zj[i] * out_scale : zj[i]);
+        for (int i = 0; i < 4; ++i) f[i] = sigmoid_fast(zj[i]);
         const int row = 8 * j + 4 * h;
         // rows past the output width and pixels past the end go beyond the
         // buffer and are dropped by its range check
@@ -539,7 +559,7 @@ __device__ __forceinline__ void mlp_store(const DecodeArgs &a, const MfmaWeights
                                           const typename P::Frag (&bx)[NT], int t0, int salt) {
   f32x16 z[NT];
   mlp_compute<P, HID, NL, NT, UNIT>(W, bias, bx, z, salt);
-  store_outputs<P, NT, VEC4>(a, P::kScaled ? W.epi[NL - 1] : 1.0f, ors, z, t0);
+  store_outputs<P, NT, VEC4>(a, ors, z, t0);
 }
 
 

@@ -94,11 +94,19 @@ __device__ __forceinline__ int frag_source_col(const MlpShape &s, bool f8, int l
   return u < s.hid ? u : -1;
 }
 
-// Scales of the E4M3 image: s_w = 448 / max|W_l|, s_a = 448 / act_amax[l];
-// stored per layer as (s_a, epilogue, s_w). The epilogue scale maps the
-// accumulator of layer l to the scaled input of layer l + 1
-// (s_a(l+1) / (s_w s_a)) or, for the last layer, to the pre-activation
-// (1 / (s_w s_a)).
+// Largest power of two <= x (x > 0 and finite).
+__device__ __forceinline__ float pow2_floor(float x) {
+  x = fminf(fmaxf(x, 0x1p-100f), 0x1p100f);  // keeps the E8M0 exponents in range
+  return ldexpf(1.0f, __builtin_amdgcn_frexp_expf(x) - 1);
+}
+
+// Scales of the E4M3 image, powers of two: s_w = 2^floor(log2(448 /
+// max|W_l|)), s_a = 2^floor(log2(448 / act_amax[l])); stored per layer as
+// (s_a, epilogue, s_w). The epilogue factor maps the accumulator of layer l
+// to the scaled input of layer l + 1 (s_a(l+1) / (s_w s_a)) or, for the
+// last layer, to the pre-activation (1 / (s_w s_a)); being a power of two,
+// the decode applies it as the E8M0 block scale of the layer's matrix
+// instructions, and the packed bias is b s_w s_a times it.
 __global__ void pack_scales_kernel(PackArgs a) {
   const int l = blockIdx.x;
   const int rows = a.p.dims[l + 1], cols = a.p.dims[l];
@@ -113,13 +121,13 @@ __global__ void pack_scales_kernel(PackArgs a) {
   }
   if (threadIdx.x == 0) {
     const float wm = red[0];
-    const float sw = wm > 0.f ? 448.0f / wm : 1.0f;
+    const float sw = wm > 0.f ? pow2_floor(448.0f / wm) : 1.0f;
     const float am = a.act_amax[l];
-    const float sa = am > 0.f ? 448.0f / am : 1.0f;
+    const float sa = am > 0.f ? pow2_floor(448.0f / am) : 1.0f;
     float epi;
     if (l + 1 < a.s.n_layers) {
       const float am2 = a.act_amax[l + 1];
-      const float sa2 = am2 > 0.f ? 448.0f / am2 : 1.0f;
+      const float sa2 = am2 > 0.f ? pow2_floor(448.0f / am2) : 1.0f;
       epi = sa2 / (sw * sa);
     } else {
       epi = 1.0f / (sw * sa);
@@ -267,7 +275,7 @@ __global__ void pack_kernel(PackArgs a, int64_t n_w_elems, int64_t n_elems) {
       const int row = 32 * m + 8 * (q >> 2) + 4 * h + (q & 3);
       const int rows = a.p.dims[l + 1];
       float v = row < rows ? a.p.b[l][row] : 0.f;
-      if (a.compute == 3) v = v * (sc[3 * l + 2] * sc[3 * l + 0]);
+      if (a.compute == 3) v = v * (sc[3 * l + 2] * sc[3 * l + 0] * sc[3 * l + 1]);
       if (a.compute == 1 && l + 1 < Ln) v = ldexpf(v, -((const int *)(a.packed + L.exp_off))[l * 64 + row]);
       ((float *)(a.packed + L.b_off[l]))[r] = v;
       return;

@@ -294,7 +294,7 @@ def test_c4_fp8_full_size_sampled(c2_case):
     err = _report("c4 fp8 4096^2", got, c["ref"])
     assert np.all(err <= TOL_FP8_ABS)
     # diagnostic: the oracle with the same E4M3 rounding and scales
-    ws, as_ = O.fp8_scales(c["Ws"], oam)
+    ws, as_ = O.fp8_scales(c["Ws"], oam, pow2=True)
     emu = O.decode_index(c["olat"], O.Mlp(c["Ws"], c["bs"], precision=O.FP8, w_scale=ws, a_scale=as_), c["uv"],
                          c["idx"])
     d = np.abs(got - emu)
