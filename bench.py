@@ -112,7 +112,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["f16", "f32", "fp8", "bwd", "batched", "copy"], default=None,
+    ap.add_argument("--only", choices=["f16", "f32", "fp8", "bwd", "qat", "batched", "copy"], default=None,
                     help="run only one leg (for profiling); 'copy' runs a plain 1 GiB device copy that "
                          "calibrates the HBM byte counters")
     ap.add_argument("--no-extras", action="store_true", help="skip backward and batched legs")
@@ -199,6 +199,41 @@ def main():
                                  "Msample_per_s": uv3.shape[0] / ms_b / 1e3,
                                  "step": "forward + L2 loss + backward (weights, biases, 1024^2..128^2 float latents)"}
         del lat3, Wt, bt, uv3t, tgt
+    if args.only in (None, "qat") and not args.no_extras:
+        log("[bench] trainable BC1 latents (2^20 samples)")
+        w3 = I.WORKLOADS["c3"]
+        _, W3, b3, uv3 = I.make_workload(w3)
+        sizes = [(w, h) for (w, h) in w3.latent_sizes]
+        rq = np.random.default_rng(6)
+        params = [torch.from_numpy((rq.standard_normal((h // 4, w // 4, ntc.QAT_PARAMS)) * 1.5)
+                                   .astype(np.float32)).to(dev).requires_grad_(True) for (w, h) in sizes]
+        Wt = [torch.from_numpy(w).to(dev).requires_grad_(True) for w in W3]
+        bt = [torch.from_numpy(b).to(dev).requires_grad_(True) for b in b3]
+        uv3t = torch.from_numpy(uv3).to(dev)
+        tgt = torch.from_numpy(I.point_sample(I.c3_targets(), uv3)).to(dev)
+
+        def qstep():
+            lat = [ntc.qat_texels_fn(p, w, h) for p, (w, h) in zip(params, sizes)]
+            o = ntc.decode_fn(uv3t, lat, Wt, bt, shift=w3.shift)
+            loss = torch.mean((o - tgt) ** 2)
+            loss.backward()
+
+        ms_q = time_launches(qstep, 5, 2)
+        pd = [p.detach() for p in params]
+        gt = [torch.randn((h, w, 3), device=dev) for (w, h) in sizes]
+        ms_fwd = time_launches(lambda: [ntc.qat_texels(p, w, h) for p, (w, h) in zip(pd, sizes)], 20, 3)
+        ms_bwd = time_launches(lambda: [ntc.qat_backward(p, w, h, g) for p, (w, h), g in zip(pd, sizes, gt)], 20, 3)
+        texels = sum(w * h for (w, h) in sizes)
+        # algorithmic bytes per texel: 88 B of logits per 16 texels, 12 B of
+        # texels (forward) or texel gradients (backward), 88 B / 16 of logit
+        # gradients written (backward)
+        fb, bb = texels * (5.5 + 12), texels * (12 + 5.5 + 5.5)
+        extras["qat_c3"] = {"ms_per_step": ms_q, "samples": int(uv3.shape[0]), "texels": texels,
+                            "qat_texels_ms": ms_fwd, "qat_backward_ms": ms_bwd,
+                            "qat_texels_GBs": fb / ms_fwd / 1e6, "qat_backward_GBs": bb / ms_bwd / 1e6,
+                            "step": "quantised texels from logits + forward + L2 loss + backward into the "
+                                    "logits, MLP weights and biases (1024^2..128^2 trainable BC1 levels)"}
+        del params, Wt, bt, uv3t, tgt, pd, gt
     if args.only in (None, "batched") and not args.no_extras:
         log("[bench] batched: 64 materials")
         specs = I.material_specs()

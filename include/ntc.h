@@ -184,6 +184,44 @@ ntc_status ntc_decode_backward(const ntc_latents *lat, const ntc_mlp *mlp, const
                                void *stream);
 
 /* ------------------------------------------------------------------------
+ * Trainable BC1 latents (Sec. 3.2, Eqs. 1-3: endpoints and interpolation
+ * weights kept as floats, a sigmoid, then quantisation to the BC1 field
+ * widths that gradients pass through unchanged).
+ *
+ * One level of width x height texels (multiples of 4, at most 16384) is a
+ * parameter array params float [height/4][width/4][22] [device]: per block
+ * the logits of endpoint 0 (r, g, b), endpoint 1 (r, g, b) and of the 16
+ * texel weights (texel (x, y) of the block at index 4 y + x). Codes:
+ * E = round(sigmoid(e) (2^b - 1)) with b = 5, 6, 5 bits for r, g, b and
+ * w = round(sigmoid(alpha) 3); a texel's value per channel is
+ * ((3 - w) E0 + w E1) / (3 (2^b - 1)), the four-colour BC1 palette. A code
+ * is the number of rounding midpoints (k + 1/2) / (2^b - 1) whose logit
+ * (correctly rounded to FP32) is at or below the parameter: the rounding of
+ * the sigmoid, with a logit equal to such an FP32 constant rounding up.
+ * NaN parameters give code 0. All three calls are stream-ordered and
+ * allocate nothing.
+ * ---------------------------------------------------------------------- */
+
+/* texels float [height][width][3] [device] = the quantised texel values
+ * (each the FP32 value nearest the exact rational, as ntc_bc1_decode_texels
+ * gives for the exported blocks). */
+ntc_status ntc_qat_texels(const float *params, int32_t width, int32_t height, float *texels, void *stream);
+
+/* grad_params float [height/4][width/4][22] [device, overwritten] from
+ * grad_texels = dL/dtexels float [height][width][3] [device], with the
+ * quantisation passed through: dL/dE0 = sum over the block's texels of
+ * (1 - w/3) g, dL/dE1 = sum of (w/3) g, dL/d(w/3) = sum over channels of
+ * (E1 - E0) g (E as values in [0, 1]), each times sigmoid'(logit). */
+ntc_status ntc_qat_backward(const float *params, int32_t width, int32_t height, const float *grad_texels,
+                            float *grad_params, void *stream);
+
+/* blocks uint64 [height/4][width/4] [device, 8-byte aligned] = BC1 blocks
+ * whose decode equals ntc_qat_texels: four-colour mode, the larger 565
+ * endpoint first (weights mirrored when the endpoints swap), and when both
+ * endpoints are equal every index 0. */
+ntc_status ntc_qat_export_bc1(const float *params, int32_t width, int32_t height, uint64_t *blocks, void *stream);
+
+/* ------------------------------------------------------------------------
  * Many materials in one launch (Sec. 4: pixels are grouped by MLP so that
  * a workgroup runs one set of weights; Alg. 1 builds per-MLP tile groups).
  * ---------------------------------------------------------------------- */

@@ -79,6 +79,9 @@ SIGNATURES = {
                                              ctypes.POINTER(_SZ)]),
     "ntc_decode_backward": (_I32, [ctypes.POINTER(ntc_latents), ctypes.POINTER(ntc_mlp), _P, _I64, _P,
                                    ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P), _P, _SZ, _P]),
+    "ntc_qat_texels": (_I32, [_P, _I32, _I32, _P, _P]),
+    "ntc_qat_backward": (_I32, [_P, _I32, _I32, _P, _P, _P]),
+    "ntc_qat_export_bc1": (_I32, [_P, _I32, _I32, _P, _P]),
     "ntc_batched_plan_size": (_I32, [ctypes.POINTER(ntc_material), _I32, ctypes.POINTER(ntc_batch_cfg),
                                      ctypes.POINTER(_SZ)]),
     "ntc_batched_plan": (_I32, [ctypes.POINTER(ntc_material), _I32, ctypes.POINTER(ntc_batch_cfg), _P, _SZ]),

@@ -280,6 +280,70 @@ def decode_fn(uv, latents: Sequence[torch.Tensor], Ws: Sequence[torch.Tensor], b
 
 
 # ---------------------------------------------------------------------------
+# Trainable BC1 latents (Sec. 3.2, Eqs. 1-3)
+# ---------------------------------------------------------------------------
+QAT_PARAMS = 22  # per block: e0 (r, g, b), e1 (r, g, b), 16 texel weights
+
+
+def _qat_check(params: torch.Tensor, width: int, height: int):
+    _require_cuda(params, "params")
+    if params.dtype != torch.float32 or not params.is_contiguous():
+        raise ValueError("params must be contiguous float32")
+    if tuple(params.shape) != (height // 4, width // 4, QAT_PARAMS):
+        raise ValueError(f"params shape {tuple(params.shape)} != {(height // 4, width // 4, QAT_PARAMS)}")
+
+
+def qat_texels(params: torch.Tensor, width: int, height: int) -> torch.Tensor:
+    """Quantised texel values [height][width][3] of a trainable BC1 level."""
+    _qat_check(params, width, height)
+    out = torch.empty((height, width, 3), dtype=torch.float32, device=params.device)
+    A.check(A.lib().ntc_qat_texels(_ptr(params), width, height, _ptr(out), _stream_handle()))
+    return out
+
+
+def qat_backward(params: torch.Tensor, width: int, height: int, grad_texels: torch.Tensor) -> torch.Tensor:
+    """Gradient w.r.t. the logits, the quantisation passed through."""
+    _qat_check(params, width, height)
+    g = grad_texels.float().contiguous()
+    if tuple(g.shape) != (height, width, 3):
+        raise ValueError("grad_texels must be [height][width][3]")
+    out = torch.empty_like(params)
+    A.check(A.lib().ntc_qat_backward(_ptr(params), width, height, _ptr(g), _ptr(out), _stream_handle()))
+    return out
+
+
+def qat_export_bc1(params: torch.Tensor, width: int, height: int) -> torch.Tensor:
+    """BC1 blocks [height/4][width/4] (uint64 bit patterns in an int64 tensor)
+    whose decode equals qat_texels."""
+    _qat_check(params, width, height)
+    out = torch.empty((height // 4, width // 4), dtype=torch.int64, device=params.device)
+    A.check(A.lib().ntc_qat_export_bc1(_ptr(params), width, height, _ptr(out), _stream_handle()))
+    return out
+
+
+class QatTexelsFn(torch.autograd.Function):
+    """texels = qat_texels(params); backward by ntc_qat_backward."""
+
+    @staticmethod
+    def forward(ctx, params, width, height):
+        p = params.detach().contiguous()
+        ctx.save_for_backward(p)
+        ctx.size = (width, height)
+        return qat_texels(p, width, height)
+
+    @staticmethod
+    def backward(ctx, grad):
+        (p,) = ctx.saved_tensors
+        w, h = ctx.size
+        return qat_backward(p, w, h, grad), None, None
+
+
+def qat_texels_fn(params: torch.Tensor, width: int, height: int) -> torch.Tensor:
+    """Differentiable quantised texels of a trainable BC1 level."""
+    return QatTexelsFn.apply(params, width, height)
+
+
+# ---------------------------------------------------------------------------
 # Many materials in one launch (Sec. 4 grouping by MLP)
 # ---------------------------------------------------------------------------
 class Material:

@@ -286,6 +286,45 @@ ntc_status ntc_bc1_decode_texels(const ntc_latents *lat, int32_t level, float *o
   return ok();
 }
 
+static ntc_status check_qat_level(const float *params, int32_t width, int32_t height) {
+  if (!params) return fail(NTC_E_NULL, "params is NULL");
+  if (!aligned(params, 4)) return fail(NTC_E_ALIGN, "params misaligned");
+  if (width < 4 || height < 4 || (width & 3) || (height & 3) || width > 16384 || height > 16384)
+    return fail(NTC_E_SHAPE, "level %d x %d: sides must be multiples of 4 in 4..16384", width, height);
+  return NTC_OK;
+}
+
+ntc_status ntc_qat_texels(const float *params, int32_t width, int32_t height, float *texels, void *stream) {
+  ntc_status st = check_qat_level(params, width, height);
+  if (st) return st;
+  if (!texels) return fail(NTC_E_NULL, "texels is NULL");
+  if (!aligned(texels, 4)) return fail(NTC_E_ALIGN, "texels misaligned");
+  hipError_t e = launch_qat_texels(params, width, height, texels, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "qat texels launch");
+  return ok();
+}
+
+ntc_status ntc_qat_backward(const float *params, int32_t width, int32_t height, const float *grad_texels,
+                            float *grad_params, void *stream) {
+  ntc_status st = check_qat_level(params, width, height);
+  if (st) return st;
+  if (!grad_texels || !grad_params) return fail(NTC_E_NULL, "grad_texels or grad_params is NULL");
+  if (!aligned(grad_texels, 4) || !aligned(grad_params, 4)) return fail(NTC_E_ALIGN, "gradients misaligned");
+  hipError_t e = launch_qat_backward(params, width, height, grad_texels, grad_params, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "qat backward launch");
+  return ok();
+}
+
+ntc_status ntc_qat_export_bc1(const float *params, int32_t width, int32_t height, uint64_t *blocks, void *stream) {
+  ntc_status st = check_qat_level(params, width, height);
+  if (st) return st;
+  if (!blocks) return fail(NTC_E_NULL, "blocks is NULL");
+  if (!aligned(blocks, 8)) return fail(NTC_E_ALIGN, "blocks must be 8-byte aligned");
+  hipError_t e = launch_qat_export(params, width, height, blocks, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "qat export launch");
+  return ok();
+}
+
 ntc_status ntc_decode_backward_workspace(const ntc_latents *lat, const ntc_mlp *mlp, int64_t n, size_t *bytes) {
   if (!bytes) return fail(NTC_E_NULL, "bytes is NULL");
   ntc_status st = check_latents(lat, false, true);

@@ -139,4 +139,17 @@ int plan_waves(int64_t n_items, int n_cus, int waves_per_cu);
 void build_plan(const BatchMaterial *mats, int n_mats, int item_tiles, int n_waves, int stage_cap, uint8_t *out,
                 size_t bytes);
 
+// Trainable BC1 levels (ntc_qat.hip): FP32 logits of the rounding
+// midpoints (k + 1/2) / M of the 5-, 6- and 2-bit fields.
+struct QatTables {
+  float mid5[31];
+  float mid6[63];
+  float mid2[3];
+};
+QatTables qat_tables();
+hipError_t launch_qat_texels(const float *params, int w, int h, float *texels, hipStream_t st);
+hipError_t launch_qat_backward(const float *params, int w, int h, const float *grad_texels, float *grad_params,
+                               hipStream_t st);
+hipError_t launch_qat_export(const float *params, int w, int h, uint64_t *blocks, hipStream_t st);
+
 }  // namespace ntc
