@@ -13,6 +13,7 @@ paths, the backward and the batched decode are reported beside it.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -270,7 +271,56 @@ def main():
                                 "per_material_Gtexel_per_s": npx / ms_many / 1e6,
                                 "waves": plan.header()["n_waves"], "autotuned": best,
                                 "autotune_ms": {json.dumps(c, sort_keys=True): round(ms, 3) for c, ms in table}}
-        del mats, plan
+        del plan
+
+        # a 4096^2 frame over the same 64 materials: classification of its
+        # 8x4 tiles, uv gather, one batched decode, output scatter
+        log("[bench] frame: 4096^2, 64 materials, classification + batched decode")
+        fw = fh = 4096
+        mat_ids = torch.from_numpy(I.material_frame(np.random.default_rng(7), fw, fh, len(mats),
+                                                    noise=0.002)).to(dev)
+        uv_img = torch.from_numpy(I.pixel_uv(fw, fh)).to(dev)
+        fd = ntc.FrameDecoder([(m.lat, m.mlp) for m in mats], cfg=ntc.batch_cfg(
+            n_cus=ntc.api._device_cus(dev), **best))
+        fp = fd.plan(mat_ids, uv_img)
+        n_valid = int(fp["pixel_list"].shape[0])
+        A = ntc.api.A
+        ws = ctypes.c_size_t(0)
+        A.check(A.lib().ntc_classify_workspace(fw, fh, len(mats), ctypes.byref(ws)))
+        cw = torch.empty(ws.value, dtype=torch.uint8, device=dev)
+        cl = torch.empty(fw * fh, dtype=torch.int32, device=dev)
+        co = torch.empty(len(mats) + 1, dtype=torch.int32, device=dev)
+        cs = torch.empty(len(mats), dtype=torch.int32, device=dev)
+        ct = torch.empty(((fw + 7) // 8) * ((fh + 3) // 4), dtype=torch.uint8, device=dev)
+        sh = ntc.api._stream_handle()
+
+        def classify_only():
+            A.check(A.lib().ntc_classify(mat_ids.data_ptr(), fw, fh, len(mats), cl.data_ptr(), co.data_ptr(),
+                                         cs.data_ptr(), ct.data_ptr(), cw.data_ptr(), ws.value, sh))
+
+        out_img = torch.zeros((fh, fw, 8), dtype=torch.float32, device=dev)
+        ms_cls = time_launches(classify_only, 20, 3)
+        ms_gat = time_launches(lambda: ntc.gather_uv(uv_img, fp["pixel_list"]), 20, 3)
+        ms_dec = time_launches(fp["plan"].launch, 10, 2)
+        ms_sca = time_launches(lambda: ntc.scatter_rows(fp["rows"], fp["pixel_list"], out_img), 20, 3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            fd.decode(mat_ids, uv_img, out=out_img)
+        torch.cuda.synchronize()
+        ms_e2e = (time.perf_counter() - t0) / 3 * 1e3
+        gpu_ms = ms_cls + ms_gat + ms_dec + ms_sca
+        tcls = fp["tile_class"].cpu().numpy()
+        extras["frame_c5"] = {"pixels": fw * fh, "neural_pixels": n_valid,
+                              "tiles": {"none": int((tcls == 0).sum()), "simple": int((tcls == 1).sum()),
+                                        "mixed": int((tcls == 2).sum())},
+                              "classify_ms": ms_cls, "gather_ms": ms_gat, "decode_ms": ms_dec,
+                              "scatter_ms": ms_sca, "gpu_ms": gpu_ms,
+                              "Gtexel_per_s": n_valid / gpu_ms / 1e6,
+                              "classify_GBs": (2 * 2 * fw * fh + 4 * n_valid) / ms_cls / 1e6,
+                              "end_to_end_ms": ms_e2e,
+                              "note": "end_to_end includes the host batch plan of each frame"}
+        del mats, fd, fp, mat_ids, uv_img, out_img, cw, cl
 
     cpu = None
     errs = {}

@@ -42,6 +42,7 @@ extern "C" {
 
 #define NTC_MAX_LEVELS 4
 #define NTC_MAX_LAYERS 5
+#define NTC_MAX_CLASSIFY_MATERIALS 4096
 
 typedef enum {
     NTC_OK = 0,
@@ -220,6 +221,49 @@ ntc_status ntc_qat_backward(const float *params, int32_t width, int32_t height, 
  * endpoint first (weights mirrored when the endpoints swap), and when both
  * endpoints are equal every index 0. */
 ntc_status ntc_qat_export_bc1(const float *params, int32_t width, int32_t height, uint64_t *blocks, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Classification of a frame by material (Sec. 4 "Tile-based
+ * classification", Algorithm 1): the screen is cut into 8x4-pixel tiles; a
+ * tile whose valid pixels all use one material and number more than 16 is
+ * "simple" and is decoded as it stands, the pixels of every other tile are
+ * regrouped by material. The result feeds the batched decode.
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes for ntc_classify. [host] */
+ntc_status ntc_classify_workspace(int32_t width, int32_t height, int32_t n_mats, size_t *bytes);
+
+/* mat_ids uint16 [height][width] [device]: the material (MLP) of each pixel;
+ * ids >= n_mats mark pixels without a neural material. width, height in
+ * 1..32768 (fewer than 2^31 pixels); n_mats in 1..NTC_MAX_CLASSIFY_MATERIALS.
+ * Tiles are numbered row-major, tile (tx, ty) covering pixels
+ * [8 tx, 8 tx + 8) x [4 ty, 4 ty + 4) (clipped at the frame edge).
+ * Outputs [device, overwritten]:
+ *   pixel_list  int32 [width height]: the indices y width + x of the valid
+ *               pixels, grouped by material in material order; inside a
+ *               material first the pixels of its simple tiles, then its
+ *               other pixels, each part in tile order and row-major inside
+ *               a tile (entries past the valid count are left untouched);
+ *   mat_offsets int32 [n_mats + 1]: material m occupies
+ *               [mat_offsets[m], mat_offsets[m + 1]); mat_offsets[n_mats] is
+ *               the number of valid pixels;
+ *   mat_simple  int32 [n_mats]: how many of them come from simple tiles;
+ *   tile_class  uint8 [tiles] or NULL: 0 no valid pixel, 1 simple, 2 other.
+ * The order is fixed (no atomics decide it): the same input gives the same
+ * lists. workspace [device, 256-byte aligned] of ntc_classify_workspace
+ * bytes. */
+ntc_status ntc_classify(const uint16_t *mat_ids, int32_t width, int32_t height, int32_t n_mats, int32_t *pixel_list,
+                        int32_t *mat_offsets, int32_t *mat_simple, uint8_t *tile_class, void *workspace,
+                        size_t ws_bytes, void *stream);
+
+/* uv[i] = uv_image[pixel_list[i]] for i < n: uv_image float [pixels][2],
+ * uv float [n][2] [device, 8-byte aligned]. */
+ntc_status ntc_gather_uv(const float *uv_image, const int32_t *pixel_list, int64_t n, float *uv, void *stream);
+
+/* image[pixel_list[i]][c] = rows[i][c] for i < n, c < channels (1..16), dtype
+ * NTC_F32 or NTC_F16 [device]. */
+ntc_status ntc_scatter_rows(const void *rows, const int32_t *pixel_list, int64_t n, int32_t channels, int32_t dtype,
+                            void *image, void *stream);
 
 /* ------------------------------------------------------------------------
  * Many materials in one launch (Sec. 4: pixels are grouped by MLP so that

@@ -339,6 +339,37 @@ def make_material(spec: MaterialSpec, bias: str = "zero"):
     return lat, Ws, bs
 
 
+def material_frame(rng: np.random.Generator, width: int, height: int, n_mats: int, n_cells: int = 0,
+                   background: float = 0.15, noise: float = 0.0) -> np.ndarray:
+    """uint16 [height][width] material ids of a synthetic frame: Voronoi cells
+    around n_cells seeds (default 2 n_mats), each cell one material (drawn
+    uniformly) or, with probability ``background``, no neural material
+    (id 0xFFFF); a fraction ``noise`` of pixels then gets a random id (or
+    background), which makes isolated mixed tiles."""
+    n_cells = n_cells or 2 * n_mats
+    sx = rng.random(n_cells) * width
+    sy = rng.random(n_cells) * height
+    cell_mat = rng.integers(0, n_mats, n_cells).astype(np.uint16)
+    cell_mat[rng.random(n_cells) < background] = 0xFFFF
+    out = np.empty((height, width), np.uint16)
+    xs = np.arange(width, dtype=np.float64) + 0.5
+    for y0 in range(0, height, 64):
+        ys = np.arange(y0, min(y0 + 64, height), dtype=np.float64)[:, None] + 0.5
+        best = np.full((ys.shape[0], width), np.inf)
+        arg = np.zeros((ys.shape[0], width), np.int64)
+        for c in range(n_cells):
+            d = (xs[None, :] - sx[c]) ** 2 + (ys - sy[c]) ** 2
+            closer = d < best
+            best[closer] = d[closer]
+            arg[closer] = c
+        out[y0:y0 + ys.shape[0]] = cell_mat[arg]
+    if noise > 0:
+        hit = rng.random((height, width)) < noise
+        ids = rng.integers(0, n_mats + 1, int(hit.sum()))
+        out[hit] = np.where(ids == n_mats, 0xFFFF, ids).astype(np.uint16)
+    return out
+
+
 def pixel_uv_torch(width: int, height: int, order: str = "tiled", device="cuda"):
     """Pixel-centre uv of every screen pixel as a float32 [W*H][2] torch tensor
     built on `device` (same values as pixel_uv without jitter)."""

@@ -403,3 +403,97 @@ class BatchPlan:
 
 def _device_cus(device="cuda") -> int:
     return torch.cuda.get_device_properties(torch.device(device)).multi_processor_count
+
+
+# ---------------------------------------------------------------------------
+# Frame classification by material and the frame decode it feeds
+# (Sec. 4 "Tile-based classification", Algorithm 1)
+# ---------------------------------------------------------------------------
+def classify(mat_ids: torch.Tensor, n_mats: int, tile_class: bool = True):
+    """Classify the 8x4 tiles of a frame (uint16 material ids [H][W]; ids >=
+    n_mats are not neural). Returns (pixel_list int32 [valid], mat_offsets
+    int32 [n_mats + 1], mat_simple int32 [n_mats], tile_class uint8 [tiles]
+    or None); pixel_list is sliced to the valid count, which takes one
+    device-to-host copy of mat_offsets[n_mats]."""
+    _require_cuda(mat_ids, "mat_ids")
+    if mat_ids.dtype not in (torch.uint16, torch.int16) or mat_ids.dim() != 2 or not mat_ids.is_contiguous():
+        raise ValueError("mat_ids must be a contiguous [H][W] uint16 (or int16 bit pattern) tensor")
+    h, w = mat_ids.shape
+    dev = mat_ids.device
+    ws = ctypes.c_size_t(0)
+    check(A.lib().ntc_classify_workspace(w, h, n_mats, ctypes.byref(ws)))
+    work = torch.empty(max(ws.value, 1), dtype=torch.uint8, device=dev)
+    lst = torch.empty(w * h, dtype=torch.int32, device=dev)
+    off = torch.empty(n_mats + 1, dtype=torch.int32, device=dev)
+    simple = torch.empty(n_mats, dtype=torch.int32, device=dev)
+    tiles = ((w + 7) // 8) * ((h + 3) // 4)
+    tcls = torch.empty(tiles, dtype=torch.uint8, device=dev) if tile_class else None
+    check(A.lib().ntc_classify(_ptr(mat_ids), w, h, n_mats, _ptr(lst), _ptr(off), _ptr(simple), _ptr(tcls),
+                               _ptr(work), ctypes.c_size_t(ws.value), _stream_handle()))
+    n = int(off[n_mats].item())
+    return lst[:n], off, simple, tcls
+
+
+def gather_uv(uv_image: torch.Tensor, pixel_list: torch.Tensor) -> torch.Tensor:
+    """uv of the listed pixels: uv_image float [H*W][2] (or [H][W][2])."""
+    _require_cuda(uv_image, "uv_image")
+    uvi = uv_image.reshape(-1, 2)
+    if uvi.dtype != torch.float32 or not uvi.is_contiguous():
+        raise ValueError("uv_image must be contiguous float32")
+    n = pixel_list.shape[0]
+    out = torch.empty((n, 2), dtype=torch.float32, device=uv_image.device)
+    check(A.lib().ntc_gather_uv(_ptr(uvi), _ptr(pixel_list), n, _ptr(out), _stream_handle()))
+    return out
+
+
+def scatter_rows(rows: torch.Tensor, pixel_list: torch.Tensor, image: torch.Tensor) -> None:
+    """image[pixel_list[i]] = rows[i]; image [H*W][C] (or [H][W][C]) of the rows' dtype."""
+    _require_cuda(rows, "rows")
+    img = image.reshape(-1, rows.shape[1])
+    if img.data_ptr() != image.data_ptr() or not image.is_contiguous() or image.dtype != rows.dtype:
+        raise ValueError("image must be contiguous with the rows' dtype")
+    check(A.lib().ntc_scatter_rows(_ptr(rows), _ptr(pixel_list), rows.shape[0], rows.shape[1],
+                                   OUT_DTYPES[rows.dtype], _ptr(img), _stream_handle()))
+
+
+class FrameDecoder:
+    """Decode a frame whose pixels use several neural materials: classify
+    the tiles, gather the uv of every material's pixels, decode them with
+    one batched launch (FP16 matrix cores) and scatter the outputs back.
+    materials: sequence of (Latents, Mlp) with a common output width."""
+
+    def __init__(self, materials, cfg=None, out_dtype=torch.float32, device="cuda"):
+        self.materials = list(materials)
+        widths = {m.n_out for _, m in self.materials}
+        if len(widths) != 1:
+            raise ValueError("materials must share the output width")
+        self.n_out = widths.pop()
+        self.packed = [pack(m, "f16") for _, m in self.materials]
+        self.cfg, self.out_dtype, self.device = cfg, out_dtype, device
+
+    def plan(self, mat_ids: torch.Tensor, uv_image: torch.Tensor):
+        """Classification, gathered uv and the batch plan of one frame."""
+        lst, off, simple, tcls = classify(mat_ids, len(self.materials))
+        uv = gather_uv(uv_image, lst)
+        rows = torch.empty((lst.shape[0], self.n_out), dtype=self.out_dtype, device=self.device)
+        offs = off.cpu().tolist()
+        mats = []
+        for m, (lat, mlp) in enumerate(self.materials):
+            a, b = offs[m], offs[m + 1]
+            if b > a:
+                mats.append(Material(lat, mlp, uv[a:b], out=rows[a:b], packed=self.packed[m]))
+        plan = BatchPlan(mats, self.cfg, device=self.device) if mats else None
+        return dict(pixel_list=lst, mat_offsets=off, mat_simple=simple, tile_class=tcls, uv=uv, rows=rows,
+                    plan=plan, materials=mats)
+
+    def decode(self, mat_ids: torch.Tensor, uv_image: torch.Tensor, out: Optional[torch.Tensor] = None):
+        """Output image [H][W][C]; pixels without a neural material keep the
+        value of `out` (zero when it is not given)."""
+        h, w = mat_ids.shape
+        if out is None:
+            out = torch.zeros((h, w, self.n_out), dtype=self.out_dtype, device=self.device)
+        p = self.plan(mat_ids, uv_image)
+        if p["plan"] is not None:
+            p["plan"].launch()
+            scatter_rows(p["rows"], p["pixel_list"], out)
+        return out

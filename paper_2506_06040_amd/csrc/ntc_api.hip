@@ -325,6 +325,64 @@ ntc_status ntc_qat_export_bc1(const float *params, int32_t width, int32_t height
   return ok();
 }
 
+static ntc_status check_frame(int32_t width, int32_t height, int32_t n_mats) {
+  if (width < 1 || height < 1 || width > 32768 || height > 32768 || (int64_t)width * height >= ((int64_t)1 << 31))
+    return fail(NTC_E_SHAPE, "frame %d x %d outside 1..32768 per side or 2^31 pixels", width, height);
+  if (n_mats < 1 || n_mats > NTC_MAX_CLASSIFY_MATERIALS)
+    return fail(NTC_E_SHAPE, "n_mats %d outside 1..%d", n_mats, NTC_MAX_CLASSIFY_MATERIALS);
+  return NTC_OK;
+}
+
+ntc_status ntc_classify_workspace(int32_t width, int32_t height, int32_t n_mats, size_t *bytes) {
+  if (!bytes) return fail(NTC_E_NULL, "bytes is NULL");
+  ntc_status st = check_frame(width, height, n_mats);
+  if (st) return st;
+  *bytes = classify_workspace_bytes(width, height, n_mats);
+  return ok();
+}
+
+ntc_status ntc_classify(const uint16_t *mat_ids, int32_t width, int32_t height, int32_t n_mats, int32_t *pixel_list,
+                        int32_t *mat_offsets, int32_t *mat_simple, uint8_t *tile_class, void *workspace,
+                        size_t ws_bytes, void *stream) {
+  ntc_status st = check_frame(width, height, n_mats);
+  if (st) return st;
+  if (!mat_ids || !pixel_list || !mat_offsets || !mat_simple || !workspace)
+    return fail(NTC_E_NULL, "mat_ids, pixel_list, mat_offsets, mat_simple or workspace is NULL");
+  if (!aligned(mat_ids, 2) || !aligned(pixel_list, 4) || !aligned(mat_offsets, 4) || !aligned(mat_simple, 4) ||
+      !aligned(workspace, 256))
+    return fail(NTC_E_ALIGN, "misaligned classification buffer");
+  const size_t need = classify_workspace_bytes(width, height, n_mats);
+  if (ws_bytes < need) return fail(NTC_E_WORKSPACE, "classification needs %zu workspace bytes, got %zu", need, ws_bytes);
+  hipError_t e = launch_classify(mat_ids, width, height, n_mats, pixel_list, mat_offsets, mat_simple, tile_class,
+                                 workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "classification launch");
+  return ok();
+}
+
+ntc_status ntc_gather_uv(const float *uv_image, const int32_t *pixel_list, int64_t n, float *uv, void *stream) {
+  if (n < 0) return fail(NTC_E_SHAPE, "n < 0");
+  if (n == 0) return ok();
+  if (!uv_image || !pixel_list || !uv) return fail(NTC_E_NULL, "uv_image, pixel_list or uv is NULL");
+  if (!aligned(uv_image, 8) || !aligned(uv, 8) || !aligned(pixel_list, 4)) return fail(NTC_E_ALIGN, "misaligned");
+  hipError_t e = launch_gather_uv(uv_image, pixel_list, n, uv, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gather launch");
+  return ok();
+}
+
+ntc_status ntc_scatter_rows(const void *rows, const int32_t *pixel_list, int64_t n, int32_t channels, int32_t dtype,
+                            void *image, void *stream) {
+  if (n < 0) return fail(NTC_E_SHAPE, "n < 0");
+  if (channels < 1 || channels > 16) return fail(NTC_E_SHAPE, "channels %d outside 1..16", channels);
+  if (dtype != NTC_F32 && dtype != NTC_F16) return fail(NTC_E_UNSUPPORTED, "dtype %d", dtype);
+  if (n == 0) return ok();
+  if (!rows || !pixel_list || !image) return fail(NTC_E_NULL, "rows, pixel_list or image is NULL");
+  const int eb = dtype == NTC_F32 ? 4 : 2;
+  if (!aligned(rows, eb) || !aligned(image, eb) || !aligned(pixel_list, 4)) return fail(NTC_E_ALIGN, "misaligned");
+  hipError_t e = launch_scatter_rows(rows, pixel_list, n, channels, eb, image, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "scatter launch");
+  return ok();
+}
+
 ntc_status ntc_decode_backward_workspace(const ntc_latents *lat, const ntc_mlp *mlp, int64_t n, size_t *bytes) {
   if (!bytes) return fail(NTC_E_NULL, "bytes is NULL");
   ntc_status st = check_latents(lat, false, true);

@@ -152,4 +152,13 @@ hipError_t launch_qat_backward(const float *params, int w, int h, const float *g
                                hipStream_t st);
 hipError_t launch_qat_export(const float *params, int w, int h, uint64_t *blocks, hipStream_t st);
 
+// Frame classification (ntc_classify.hip).
+int classify_chunks(int w, int h);
+size_t classify_workspace_bytes(int w, int h, int n_mats);
+hipError_t launch_classify(const uint16_t *mat, int w, int h, int n_mats, int32_t *list, int32_t *mat_offsets,
+                           int32_t *mat_simple, uint8_t *tile_class, void *workspace, hipStream_t st);
+hipError_t launch_gather_uv(const float *uv_image, const int32_t *list, int64_t n, float *uv, hipStream_t st);
+hipError_t launch_scatter_rows(const void *rows, const int32_t *list, int64_t n, int c, int elem_bytes, void *image,
+                               hipStream_t st);
+
 }  // namespace ntc
