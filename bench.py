@@ -113,7 +113,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["f16", "f32", "fp8", "bwd", "qat", "batched", "copy"], default=None,
+    ap.add_argument("--only", choices=["f16", "f32", "fp8", "bf16", "varA", "bwd", "qat", "batched", "copy"],
+                    default=None,
                     help="run only one leg (for profiling); 'copy' runs a plain 1 GiB device copy that "
                          "calibrates the HBM byte counters")
     ap.add_argument("--no-extras", action="store_true", help="skip backward and batched legs")
@@ -178,8 +179,25 @@ def main():
         ms8 = leg("fp8", p8, args.steps, args.warmup)
         gpu_out["fp8"] = out.cpu().numpy()
         result["fp8_ms"] = ms8
+    if args.only in (None, "bf16"):
+        log("[bench] BF16 matrix-core decode")
+        pb = ntc.pack(mlp, "bf16")
+        msb = leg("bf16", pb, args.steps, args.warmup)
+        gpu_out["bf16"] = out.cpu().numpy()
+        result["bf16_ms"] = msb
 
     extras = {}
+    if args.only in (None, "varA") and not args.no_extras:
+        # latent layout variant A of the paper: levels at W, W, W/2, W/2
+        log("[bench] FP16 decode, latent layout variant A (4096^2, 4096^2, 2048^2, 2048^2)")
+        sizes_a = [(4096, 4096), (4096, 4096), (2048, 2048), (2048, 2048)]
+        lat_a = ntc.Latents(I.bc1_pyramid(I.streams(wl.seed + 100)[0], sizes_a), shift=wl.shift, device=dev)
+        fa = lambda: ntc.decode(lat_a, mlp, uvt, compute="f16", packed=p16, out=out)
+        ms_a = time_launches(fa, args.steps, args.warmup)
+        extras["varA_f16"] = {"Gtexel_per_s": N / (ms_a * 1e-3) / 1e9, "ms": ms_a,
+                              "frac_fp16_mfma": flops / (ms_a * 1e-3) / 1e12 / PEAK_FP16_TFLOPS,
+                              "latents": sizes_a}
+        del lat_a
     if args.only in (None, "bwd") and not args.no_extras:
         log("[bench] backward (2^20 samples)")
         w3 = I.WORKLOADS["c3"]
@@ -373,6 +391,10 @@ def main():
         g8 = N / (result["fp8_ms"] * 1e-3) / 1e9
         line["fp8"] = {"Gtexel_per_s": round(g8, 3), "ms": round(result["fp8_ms"], 4),
                        "frac_fp8_mfma": round(flops / (result["fp8_ms"] * 1e-3) / 1e12 / PEAK_FP8_TFLOPS, 4)}
+    if "bf16_ms" in result:
+        gb = N / (result["bf16_ms"] * 1e-3) / 1e9
+        line["bf16"] = {"Gtexel_per_s": round(gb, 3), "ms": round(result["bf16_ms"], 4),
+                        "frac_bf16_mfma": round(flops / (result["bf16_ms"] * 1e-3) / 1e12 / PEAK_FP16_TFLOPS, 4)}
     if errs:
         line["err_vs_oracle"] = errs
     line.update(extras)

@@ -123,7 +123,7 @@ const char *ntc_last_error(void);
 int32_t ntc_version(void);
 
 /* Bytes of the packed weight image of `mlp` for compute type `compute`
- * (NTC_F32, NTC_F16 or NTC_FP8_E4M3). [host] */
+ * (NTC_F32, NTC_F16, NTC_BF16 or NTC_FP8_E4M3). [host] */
 ntc_status ntc_mlp_pack_size(const ntc_mlp *mlp, int32_t compute, size_t *bytes);
 
 /* Write the packed weight image used by ntc_decode: weights converted to
@@ -154,13 +154,13 @@ ntc_status ntc_calibrate_fp8(const ntc_latents *lat, const ntc_mlp *mlp, const v
 
 /* Fused decode (Sec. 3.1 + Sec. 3.3 + Sec. 4): out[s] = f(x(uv[s])) for
  * s < n. compute selects the arithmetic: NTC_F32 (plain FP32 FMAs, one
- * pixel per lane), NTC_F16 (FP16 matrix cores, FP32 accumulation) or
- * NTC_FP8_E4M3 (E4M3 matrix cores with per-layer scales, FP32
- * accumulation). packed is the image written by ntc_mlp_pack for the same
+ * pixel per lane), NTC_F16 (FP16 matrix cores, FP32 accumulation),
+ * NTC_BF16 (BF16 matrix cores, FP32 accumulation) or NTC_FP8_E4M3 (E4M3
+ * matrix cores with per-layer scales, FP32 accumulation). packed is the image written by ntc_mlp_pack for the same
  * compute type. uv float [n][2] [device, 8-byte aligned]; out [n][C]
  * with C = dims[n_layers] of out_dtype NTC_F32 or NTC_F16 [device, 16-byte
  * aligned]. n may be 0 (nothing is enqueued). BC1 latents only for
- * NTC_F16 / NTC_FP8_E4M3. cfg may be NULL. */
+ * NTC_F16 / NTC_BF16 / NTC_FP8_E4M3. cfg may be NULL. */
 ntc_status ntc_decode(const ntc_latents *lat, const ntc_mlp *mlp, int32_t compute, const void *packed,
                       const float *uv, int64_t n, void *out, int32_t out_dtype,
                       const ntc_tile_cfg *cfg, void *stream);

@@ -19,7 +19,7 @@ from ._abi import NtcError, check
 PAPER_SHIFT = ((0.0, 0.0), (0.5, 0.5), (0.0, 0.0), (0.5, 0.5))
 NO_SHIFT = ((0.0, 0.0),) * 4
 
-COMPUTE = {"f32": A.F32, "f16": A.F16, "fp8": A.FP8_E4M3}
+COMPUTE = {"f32": A.F32, "f16": A.F16, "bf16": A.BF16, "fp8": A.FP8_E4M3}
 OUT_DTYPES = {torch.float32: A.F32, torch.float16: A.F16}
 
 

@@ -140,7 +140,7 @@ MlpPtrs to_mlp_ptrs(const ntc_mlp *mlp) {
   return p;
 }
 
-bool valid_compute(int c) { return c == NTC_F32 || c == NTC_F16 || c == NTC_FP8_E4M3; }
+bool valid_compute(int c) { return c == NTC_F32 || c == NTC_F16 || c == NTC_BF16 || c == NTC_FP8_E4M3; }
 
 }  // namespace
 

@@ -94,6 +94,7 @@ hipError_t launch_decode_mfma(const DecodeArgs &a, const MlpShape &s, int comput
   if (grid >= 8) grid &= ~(int64_t)7;
   if (grid < 1) grid = 1;
   if (compute == 1) return launch_mfma_prec<PrecF16>(a, s, (int)grid, st);
+  if (compute == 2) return launch_mfma_prec<PrecBF16>(a, s, (int)grid, st);
   if (compute == 3) return launch_mfma_prec<PrecF8>(a, s, (int)grid, st);
   return hipErrorInvalidValue;
 }

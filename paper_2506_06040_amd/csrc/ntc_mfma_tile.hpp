@@ -32,6 +32,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ntc_device.hpp"
 #include "ntc_internal.hpp"
 
@@ -66,6 +68,9 @@ namespace ntc {
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
@@ -108,6 +113,7 @@ struct PrecF16 {
   using Frag = half8_t;
   static constexpr int KSTEP = 16;
   static constexpr bool kScaled = false;
+  static constexpr bool kUnitReLU = true;  // packed image scaled for ReLU by clamp
   static constexpr int kFeatDwords = 4;  // dwords of a fragment that carry features
   __device__ __forceinline__ static f32x16 mma(Frag a, Frag b, f32x16 c, int, const int (&)[2]) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
@@ -142,6 +148,47 @@ struct PrecF16 {
   }
 };
 
+// BF16 operands, 32x32x16 tiles (same layout as FP16). There is no BF16
+// maximum instruction, so ReLU is a median with 0 in FP32 before the packed
+// conversion.
+struct PrecBF16 {
+  using Frag = bf16x8_t;
+  static constexpr int KSTEP = 16;
+  static constexpr bool kScaled = false;
+  static constexpr bool kUnitReLU = false;
+  static constexpr int kFeatDwords = 4;
+  __device__ __forceinline__ static f32x16 mma(Frag a, Frag b, f32x16 c, int, const int (&)[2]) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static Frag features(const float (&x)[8], float) {
+    Frag f;
+#pragma unroll
+    for (int i = 0; i < 8; i += 2) {
+      const f32x2 p = {x[i], x[i + 1]};
+      const bf16x2_t h = __builtin_convertvector(p, bf16x2_t);
+      f[i] = h[0];
+      f[i + 1] = h[1];
+    }
+    return f;
+  }
+  template <int MT, int KS, bool>
+  __device__ __forceinline__ static void next_operands(const f32x16 (&acc)[MT], Frag (&hb)[KS], float) {
+#pragma unroll
+    for (int c = 0; c < KS; ++c) {
+      const f32x16 &v = acc[(c >> 1) % MT];
+      const int o = 8 * (c & 1);
+#pragma unroll
+      for (int i = 0; i < 8; i += 2) {
+        const f32x2 p = {__builtin_amdgcn_fmed3f(v[o + i], 0.0f, 3.0e38f),
+                         __builtin_amdgcn_fmed3f(v[o + i + 1], 0.0f, 3.0e38f)};
+        const bf16x2_t h = __builtin_convertvector(p, bf16x2_t);
+        hb[c][i] = h[0];
+        hb[c][i + 1] = h[1];
+      }
+    }
+  }
+};
+
 // OCP E4M3 with saturation to +-448 (the conversion instruction is applied
 // to clamped values).
 __device__ __forceinline__ float sat448(float v) { return __builtin_amdgcn_fmed3f(v, -448.0f, 448.0f); }
@@ -166,6 +213,7 @@ struct PrecF8 {
   using Frag = i32x8;
   static constexpr int KSTEP = 64;
   static constexpr bool kScaled = true;
+  static constexpr bool kUnitReLU = false;
   static constexpr int kFeatDwords = 2;
   // Format 0 = E4M3 for both operands. The weights' E8M0 block scale
   // (127 + p for 2^p) carries layer l's epilogue factor: byte l % 4 of
@@ -215,7 +263,9 @@ struct PrecF8 {
 // Dword d of an operand fragment, and its replacement.
 template <class P>
 __device__ __forceinline__ unsigned dword_of(const typename P::Frag &f, int d) {
-  if constexpr (P::kFeatDwords == 4) {
+  if constexpr (std::is_same_v<typename P::Frag, bf16x8_t>) {
+    return __builtin_bit_cast(u32x4_t, f)[d];
+  } else if constexpr (P::kFeatDwords == 4) {
     const half2_t h2 = {f[2 * d], f[2 * d + 1]};
     return __builtin_bit_cast(unsigned, h2);
   } else {
@@ -225,7 +275,11 @@ __device__ __forceinline__ unsigned dword_of(const typename P::Frag &f, int d) {
 }
 template <class P>
 __device__ __forceinline__ void set_dword(typename P::Frag &f, int d, unsigned w) {
-  if constexpr (P::kFeatDwords == 4) {
+  if constexpr (std::is_same_v<typename P::Frag, bf16x8_t>) {
+    u32x4_t v = __builtin_bit_cast(u32x4_t, f);
+    v[d] = w;
+    f = __builtin_bit_cast(bf16x8_t, v);
+  } else if constexpr (P::kFeatDwords == 4) {
     const half2_t h2 = __builtin_bit_cast(half2_t, w);
     f[2 * d] = h2[0];
     f[2 * d + 1] = h2[1];
@@ -326,7 +380,7 @@ struct MfmaWeights {
     unit_relu = 0;
 #pragma unroll
     for (int l = 0; l < kMaxLayers; ++l) epi[l] = 1.0f;
-    if (!P::kScaled) unit_flag = gload(reinterpret_cast<const float *>(packed + lay.scale_off));
+    if (P::kUnitReLU) unit_flag = gload(reinterpret_cast<const float *>(packed + lay.scale_off));
     if (P::kScaled) {
       const float *sc = reinterpret_cast<const float *>(packed + lay.scale_off);
       in_scale = gload(sc);
@@ -945,7 +999,7 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
   // whose activations are known to be at most 1 (image scaled for it,
   // coordinates in the unit square); other spans take the direct path with
   // the max-based ReLU
-  if (staged && (P::kScaled || (in_unit && W.unit_relu != 0))) {
+  if (staged && (!P::kUnitReLU || (in_unit && W.unit_relu != 0))) {
     // The next span's uv is requested only now: the vector-memory counter
     // completes in order, so a load issued before the staging fetches would be
     // waited for together with them. After it come exactly the stores of the
@@ -957,7 +1011,7 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     for (int q = 0; q < ST; ++q) {
       Frag bx[2];
       staged_operands<P>(a, stage, ltab, kbw, kbase, u[q], v[q], W.in_scale, span_salt + q, bx);
-      subspan_mlp<P, HID, NL, VEC4, !P::kScaled>(a, W, bias, ors, bx, q, span_salt + 2 * q);
+      subspan_mlp<P, HID, NL, VEC4, P::kUnitReLU>(a, W, bias, ors, bx, q, span_salt + 2 * q);
     }
     return;
   }

@@ -254,6 +254,8 @@ __global__ void pack_kernel(PackArgs a, int64_t n_w_elems, int64_t n_elems) {
         if (row < rows && col >= 0 && col < cols) v = a.p.W[l][(int64_t)row * cols + col];
         if (f8) {
           (a.packed + L.w_off[l])[r] = to_e4m3(v * sc[3 * l + 2]);
+        } else if (a.compute == 2) {
+          ((__bf16 *)(a.packed + L.w_off[l]))[r] = (__bf16)v;
         } else {
           const int *ex = (const int *)(a.packed + L.exp_off);
           const int e_in = (l > 0 && col >= 0) ? ex[(l - 1) * 64 + col] : 0;

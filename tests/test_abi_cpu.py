@@ -74,7 +74,6 @@ def test_decode_validation(A):
     lat, mlp = _lat(A), _mlp(A)
     assert A.lib().ntc_decode(None, ctypes.byref(mlp), 1, 0x1000, 0x1000, 10, 0x1000, 0, None, None) == A.E_NULL
     assert _decode(A, lat, mlp, compute=7) == A.E_UNSUPPORTED
-    assert _decode(A, lat, mlp, compute=A.BF16) == A.E_UNSUPPORTED
     assert _decode(A, lat, mlp, n=-1) == A.E_SHAPE
     assert _decode(A, lat, mlp, packed=0) == A.E_NULL
     assert _decode(A, lat, mlp, packed=0x1010) == A.E_ALIGN
@@ -114,7 +113,8 @@ def test_pack_validation(A):
     assert L.ntc_mlp_pack_size(ctypes.byref(mlp), A.F16, ctypes.byref(n)) == A.OK and n.value > 0
     n32 = ctypes.c_size_t(0)
     assert L.ntc_mlp_pack_size(ctypes.byref(mlp), A.F32, ctypes.byref(n32)) == A.OK
-    assert L.ntc_mlp_pack_size(ctypes.byref(mlp), A.BF16, ctypes.byref(n)) == A.E_UNSUPPORTED
+    assert L.ntc_mlp_pack_size(ctypes.byref(mlp), A.BF16, ctypes.byref(n)) == A.OK
+    assert L.ntc_mlp_pack_size(ctypes.byref(mlp), 7, ctypes.byref(n)) == A.E_UNSUPPORTED
     assert L.ntc_mlp_pack(ctypes.byref(mlp), A.F16, None, 0x1000, 10, None) == A.E_WORKSPACE
     assert L.ntc_mlp_pack(ctypes.byref(mlp), A.F16, None, 0x1010, 1 << 20, None) == A.E_ALIGN
     assert L.ntc_mlp_pack(ctypes.byref(mlp), A.FP8_E4M3, None, 0x1000, 1 << 20, None) == A.E_NULL

@@ -17,6 +17,9 @@ pytestmark = pytest.mark.gpu
 TOL_F32_REL = 1e-5
 TOL_F16_ABS = 2e-3
 TOL_FP8_ABS = 3e-2
+# BF16 keeps 8 significant bits against FP16's 11: unit roundoff 2^-8 is
+# 8x that of FP16, so its gate is 8x the FP16 one
+TOL_BF16_ABS = 8 * TOL_F16_ABS
 
 
 def _ntc():
@@ -80,7 +83,7 @@ def test_plain_f32_c1_all_pixels():
     assert np.all(err <= TOL_F32_REL * np.abs(ref))
 
 
-@pytest.mark.parametrize("compute,tol", [("f16", TOL_F16_ABS), ("f32", None)])
+@pytest.mark.parametrize("compute,tol", [("f16", TOL_F16_ABS), ("bf16", TOL_BF16_ABS), ("f32", None)])
 def test_c1_shape_variants(compute, tol):
     """Random biases, ragged sizes, wrap addressing, no shift, uv outside [0,1],
     fewer levels, 9 output channels."""
@@ -134,7 +137,7 @@ def test_staged_equals_direct_and_deterministic():
     lat_np, Ws, bs, uv = I.make_workload(wl, bias="normal")
     lat, mlp = _gpu_case(lat_np, Ws, bs, wl.shift)
     uvt = torch.from_numpy(uv).cuda()
-    for compute in ("f16",):
+    for compute in ("f16", "bf16"):
         packed = ntc.pack(mlp, compute)
         a = ntc.decode(lat, mlp, uvt, compute=compute, packed=packed)
         b = ntc.decode(lat, mlp, uvt, compute=compute, packed=packed)
@@ -269,6 +272,38 @@ def test_c2_f16_full_size_sampled(c2_case):
     err = _report("c2 f16 4096^2", got, c["ref"])
     assert np.all(err <= TOL_F16_ABS)
     assert torch.isfinite(out).all()
+
+
+def test_c2_bf16_full_size_sampled(c2_case):
+    ntc = _ntc()
+    c = c2_case
+    out = ntc.decode(c["lat"], c["mlp"], c["uvt"], compute="bf16")
+    got = out[torch.from_numpy(c["idx"]).cuda()].cpu().numpy()
+    err = _report("c2 bf16 4096^2", got, c["ref"])
+    assert np.all(err <= TOL_BF16_ABS)
+    assert torch.isfinite(out).all()
+
+
+def test_varA_layout_parity():
+    """Variant A of the paper's latent layouts: levels at W, W, W/2, W/2 (the
+    default workloads use variant B, W, W/2, W/4, W/8)."""
+    ntc = _ntc()
+    rng = np.random.default_rng(51)
+    w = 256
+    sizes = [(w, w), (w, w), (w // 2, w // 2), (w // 2, w // 2)]
+    lat_np = I.bc1_pyramid(rng, sizes)
+    Ws, bs = I.xavier_mlp(rng, (14, 64, 64, 64, 8), bias="normal")
+    uv = I.pixel_uv(w, w, order="tiled")
+    lat, mlp = _gpu_case(lat_np, Ws, bs, I.PAPER_SHIFT)
+    uvt = torch.from_numpy(uv).cuda()
+    olat, omlp = _oracle_case(lat_np, Ws, bs, I.PAPER_SHIFT)
+    ref = O.decode(olat, omlp, uv)
+    for compute, tol in (("f16", TOL_F16_ABS), ("bf16", TOL_BF16_ABS)):
+        out = ntc.decode(lat, mlp, uvt, compute=compute)
+        direct = ntc.decode(lat, mlp, uvt, compute=compute, cfg=ntc.tile_cfg(stage_capacity=64))
+        err = _report(f"varA {compute}", out.cpu().numpy(), ref)
+        assert np.all(err <= tol)
+        assert torch.equal(out, direct)
 
 
 def test_c2_f32_full_size_sampled(c2_case):
