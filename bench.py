@@ -113,7 +113,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["f16", "f32", "fp8", "bf16", "varA", "bwd", "qat", "batched", "copy"],
+    ap.add_argument("--only", choices=["f16", "f32", "fp8", "bf16", "varA", "filtered", "bwd", "qat", "batched",
+                                       "copy"],
                     default=None,
                     help="run only one leg (for profiling); 'copy' runs a plain 1 GiB device copy that "
                          "calibrates the HBM byte counters")
@@ -198,6 +199,23 @@ def main():
                               "frac_fp16_mfma": flops / (ms_a * 1e-3) / 1e12 / PEAK_FP16_TFLOPS,
                               "latents": sizes_a}
         del lat_a
+    if args.only in (None, "filtered") and not args.no_extras:
+        # mip-mapped latents (2048^2 .. 256^2 levels, full BC1 mip chains),
+        # a 4096^2 perspective ground plane with its screen derivatives
+        log("[bench] filtered decode: 4096^2 perspective plane, trilinear and 16x anisotropic")
+        rf = I.streams(wl.seed + 200)[0]
+        chains = [I.bc1_mip_chain(rf, w, h) for (w, h) in wl.latent_sizes]
+        lm = ntc.LatentMips(chains, shift=wl.shift, device=dev)
+        uvp, duvp = I.perspective_plane(4096, 4096, far=24.0)
+        uvp_t, duvp_t = torch.from_numpy(uvp).to(dev), torch.from_numpy(duvp).to(dev)
+        res_f = {}
+        for filt, ma in (("trilinear", 1), ("anisotropic", 16)):
+            ff = lambda: ntc.decode_filtered(lm, mlp, uvp_t, duvp_t, filter=filt, max_aniso=max(ma, 1), packed=p16,
+                                             out=out)
+            ms_f = time_launches(ff, max(2, args.steps // 4), 2)
+            res_f[filt] = {"ms": ms_f, "Gtexel_per_s": N / (ms_f * 1e-3) / 1e9}
+        extras["filtered_c2"] = res_f
+        del lm, uvp_t, duvp_t, chains
     if args.only in (None, "bwd") and not args.no_extras:
         log("[bench] backward (2^20 samples)")
         w3 = I.WORKLOADS["c3"]

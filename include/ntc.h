@@ -43,6 +43,8 @@ extern "C" {
 #define NTC_MAX_LEVELS 4
 #define NTC_MAX_LAYERS 5
 #define NTC_MAX_CLASSIFY_MATERIALS 4096
+#define NTC_MAX_MIPS 12
+#define NTC_MAX_ANISO 16
 
 typedef enum {
     NTC_OK = 0,
@@ -183,6 +185,43 @@ ntc_status ntc_decode_backward(const ntc_latents *lat, const ntc_mlp *mlp, const
                                const float *grad_out, float *const *grad_W, float *const *grad_b,
                                float *const *grad_latents, void *workspace, size_t ws_bytes,
                                void *stream);
+
+/* ------------------------------------------------------------------------
+ * Mip-mapped latents and filtered sampling (Sec. 3.2: every mip of a latent
+ * texture is its own BC1 texture; Sec. 3.3: the latents are fetched with
+ * trilinear or anisotropic filtering).
+ * ---------------------------------------------------------------------- */
+typedef enum { NTC_FILTER_TRILINEAR = 1, NTC_FILTER_ANISOTROPIC = 2 } ntc_filter;
+
+typedef struct {
+    int32_t n_levels;                           /* 1 .. NTC_MAX_LEVELS */
+    int32_t n_mips[NTC_MAX_LEVELS];             /* 1 .. NTC_MAX_MIPS */
+    int32_t width[NTC_MAX_LEVELS];              /* mip 0, texels */
+    int32_t height[NTC_MAX_LEVELS];
+    float shift[NTC_MAX_LEVELS][2];             /* sampling offset in texels of each mip, |shift| <= 1 */
+    const void *data[NTC_MAX_LEVELS][NTC_MAX_MIPS]; /* BC1 blocks of mip m: (width >> m) x (height >> m)
+                                                   texels, multiples of 4 [device, 8-byte aligned] */
+} ntc_latent_mips;
+
+/* Filtered decode with FP16 matrix cores: out[s] = f(x(uv[s])) where the
+ * features of level k are filtered over its mip chain, clamp-to-edge
+ * addressing inside each mip. duv float [n][4] [device, 16-byte aligned]
+ * holds the screen derivatives (du/dx, dv/dx, du/dy, dv/dy) of each
+ * sample. With the footprint axes measured in texels of mip 0,
+ * Px = |(du/dx W, dv/dx H)|, Py = |(du/dy W, dv/dy H)|:
+ *   NTC_FILTER_TRILINEAR: lod = log2 max(Px, Py), clamped to [0, n_mips - 1];
+ *     the bilinear samples of mips floor(lod) and floor(lod) + 1 are blended
+ *     by the fraction of lod;
+ *   NTC_FILTER_ANISOTROPIC: N = min(ceil(Pmax / Pmin), max_aniso) trilinear
+ *     samples at lod = log2(Pmax / N) along the longer axis, at
+ *     uv + (i / (N + 1) - 1/2) (du, dv) for i = 1..N, averaged. N is the
+ *     smallest n with n^2 Pmin^2 >= Pmax^2, with the squared lengths and that
+ *     product rounded as FP32 operations in this order (no fused multiply-add).
+ * max_aniso in 1..NTC_MAX_ANISO. packed is the NTC_F16 image of mlp; uv,
+ * out and out_dtype as for ntc_decode. */
+ntc_status ntc_decode_filtered(const ntc_latent_mips *lat, const ntc_mlp *mlp, const void *packed, const float *uv,
+                               const float *duv, int64_t n, void *out, int32_t out_dtype, int32_t filter,
+                               int32_t max_aniso, void *stream);
 
 /* ------------------------------------------------------------------------
  * Trainable BC1 latents (Sec. 3.2, Eqs. 1-3: endpoints and interpolation

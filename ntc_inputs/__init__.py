@@ -339,6 +339,39 @@ def make_material(spec: MaterialSpec, bias: str = "zero"):
     return lat, Ws, bs
 
 
+def bc1_mip_chain(rng: np.random.Generator, width: int, height: int, n_mips: int = 0) -> List[np.ndarray]:
+    """BC1 mips of one latent level, mip m of (width >> m) x (height >> m)
+    texels, each drawn independently like bc1_level (the mips of a trained
+    level are separate textures); n_mips = 0: down to 4 texels on the short side."""
+    if not n_mips:
+        n_mips = int(np.log2(min(width, height) // 4)) + 1
+    return [bc1_level(rng, width >> m, height >> m) for m in range(n_mips)]
+
+
+def perspective_plane(width: int, height: int, far: float = 20.0):
+    """(uv float32 [W*H][2], duv float32 [W*H][4]) of a textured ground plane
+    seen in perspective, pixels row-major: row y is at distance
+    z = 1 / (1/far + (1 - 1/far) (y + 1/2) / height) (far at the top),
+    u = 1/2 + (x + 1/2 - width/2) z / (width far), v = (far - z) / (far - 1);
+    duv = (du/dx, dv/dx, du/dy, dv/dy) analytically. Near rows are isotropic,
+    far rows stretched along v by up to `far` : 1."""
+    x = (np.arange(width, dtype=np.float64) + 0.5)[None, :]
+    t = (np.arange(height, dtype=np.float64) + 0.5)[:, None] / height
+    a = 1.0 / far
+    z = 1.0 / (a + (1.0 - a) * t)
+    dzdy = -(1.0 - a) / height * z * z
+    cx = (x - width / 2) / (width * far)
+    u = 0.5 + cx * z
+    v = (far - z) / (far - 1.0) + 0.0 * x
+    dudx = z / (width * far) + 0.0 * x
+    dudy = cx * dzdy
+    dvdx = np.zeros_like(u)
+    dvdy = -dzdy / (far - 1.0) + 0.0 * x
+    uv = np.stack([u, v], axis=-1).reshape(-1, 2).astype(np.float32)
+    duv = np.stack([dudx, dvdx, dudy, dvdy], axis=-1).reshape(-1, 4).astype(np.float32)
+    return uv, duv
+
+
 def material_frame(rng: np.random.Generator, width: int, height: int, n_mats: int, n_cells: int = 0,
                    background: float = 0.15, noise: float = 0.0) -> np.ndarray:
     """uint16 [height][width] material ids of a synthetic frame: Voronoi cells

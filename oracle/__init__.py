@@ -183,6 +183,17 @@ def features(lat: Latents, uv: np.ndarray, threads: int = 0) -> np.ndarray:
     return x
 
 
+def mlp_forward(mlp: Mlp, x: np.ndarray, threads: int = 0) -> np.ndarray:
+    """f(x) for given feature vectors x [n][dims[0]], float64 [n][C]."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n = x.shape[0]
+    assert x.shape[1] == mlp.dims[0]
+    out = np.empty((n, mlp.dims[-1]), np.float64)
+    _load().oracle_mlp_forward(ctypes.byref(mlp.c), _ptr(x), ctypes.c_int64(n), _ptr(out),
+                               ctypes.c_int32(threads or default_threads()))
+    return out
+
+
 def decode(lat: Latents, mlp: Mlp, uv: np.ndarray, threads: int = 0) -> np.ndarray:
     """p(uv) = f(x(uv)) for every sample, float64 [n][C]."""
     uv = np.ascontiguousarray(uv, dtype=np.float64)

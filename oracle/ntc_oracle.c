@@ -265,6 +265,13 @@ static void mlp_one(const oracle_mlp *m, const double *x, double *f, double *z_a
     for (int o = 0; o < m->dims[m->n_layers]; ++o) f[o] = h[o];
 }
 
+/* The MLP alone on given feature vectors: out[s] = f(x[s]), x [n][dims[0]]. */
+void oracle_mlp_forward(const oracle_mlp *m, const double *x, int64_t n, double *out, int32_t threads) {
+    int32_t d0 = m->dims[0], C = m->dims[m->n_layers];
+#pragma omp parallel for schedule(dynamic, 256) num_threads(threads > 0 ? threads : 1)
+    for (int64_t s = 0; s < n; ++s) mlp_one(m, x + s * d0, out + s * C, NULL, NULL);
+}
+
 /* Full decode p(uv) = f(x(uv)) for n samples: out [n][C]. */
 void oracle_decode(const oracle_level *lv, int32_t n_levels, int32_t mode, const oracle_mlp *m,
                    const double *uv, int64_t n, double *out, int32_t threads) {

@@ -10,6 +10,6 @@ from .api import (  # noqa: F401
     NO_SHIFT, PAPER_SHIFT, BatchPlan, Latents, Material, Mlp, NtcDecodeFn, batch_cfg, bc1_decode_texels,
     calibrate_fp8, decode, decode_backward, decode_fn, pack, pack_size, tile_cfg,
     QAT_PARAMS, QatTexelsFn, qat_backward, qat_export_bc1, qat_texels, qat_texels_fn,
-    FrameDecoder, classify, gather_uv, scatter_rows,
+    FrameDecoder, classify, gather_uv, scatter_rows, LatentMips, decode_filtered,
 )
 from . import autotune  # noqa: F401,E402

@@ -60,6 +60,17 @@ class ntc_batch_cfg(ctypes.Structure):
                 ("stage_capacity", ctypes.c_int32), ("n_cus", ctypes.c_int32)]
 
 
+MAX_MIPS = 12
+FILTER_TRILINEAR, FILTER_ANISOTROPIC = 1, 2
+
+
+class ntc_latent_mips(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("n_mips", ctypes.c_int32 * MAX_LEVELS),
+                ("width", ctypes.c_int32 * MAX_LEVELS), ("height", ctypes.c_int32 * MAX_LEVELS),
+                ("shift", (ctypes.c_float * 2) * MAX_LEVELS),
+                ("data", (ctypes.c_void_p * MAX_MIPS) * MAX_LEVELS)]
+
+
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _I64 = ctypes.c_int64
@@ -79,6 +90,8 @@ SIGNATURES = {
                                              ctypes.POINTER(_SZ)]),
     "ntc_decode_backward": (_I32, [ctypes.POINTER(ntc_latents), ctypes.POINTER(ntc_mlp), _P, _I64, _P,
                                    ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P), _P, _SZ, _P]),
+    "ntc_decode_filtered": (_I32, [ctypes.POINTER(ntc_latent_mips), ctypes.POINTER(ntc_mlp), _P, _P, _P, _I64, _P,
+                                   _I32, _I32, _I32, _P]),
     "ntc_qat_texels": (_I32, [_P, _I32, _I32, _P, _P]),
     "ntc_qat_backward": (_I32, [_P, _I32, _I32, _P, _P, _P]),
     "ntc_qat_export_bc1": (_I32, [_P, _I32, _I32, _P, _P]),

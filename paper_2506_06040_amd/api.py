@@ -497,3 +497,66 @@ class FrameDecoder:
             p["plan"].launch()
             scatter_rows(p["rows"], p["pixel_list"], out)
         return out
+
+
+# ---------------------------------------------------------------------------
+# Mip-mapped latents and filtered sampling (Sec. 3.2 mip chains, Sec. 3.3)
+# ---------------------------------------------------------------------------
+FILTERS = {"trilinear": A.FILTER_TRILINEAR, "anisotropic": A.FILTER_ANISOTROPIC}
+
+
+class LatentMips:
+    """Latent levels with a BC1 mip chain each: levels[k][m] is the block
+    array (uint64 / int64 [(H_k >> m)/4][(W_k >> m)/4]) of mip m of level k.
+    shift: per-level sampling offset in texels of each mip."""
+
+    def __init__(self, levels: Sequence[Sequence], shift=PAPER_SHIFT, device="cuda"):
+        if not 1 <= len(levels) <= A.MAX_LEVELS:
+            raise ValueError("1..4 latent levels")
+        self.tensors = []
+        c = A.ntc_latent_mips()
+        c.n_levels = len(levels)
+        self.shift = tuple(tuple(map(float, s)) for s in shift[:len(levels)])
+        self.sizes = []
+        for k, chain in enumerate(levels):
+            if not 1 <= len(chain) <= A.MAX_MIPS:
+                raise ValueError(f"level {k}: 1..{A.MAX_MIPS} mips")
+            ts = []
+            for b in chain:
+                t = torch.from_numpy(np.ascontiguousarray(b).view(np.int64)) if isinstance(b, np.ndarray) else b
+                ts.append(t.to(device))
+            self.tensors.append(ts)
+            h, w = ts[0].shape[0] * 4, ts[0].shape[1] * 4
+            self.sizes.append((w, h))
+            c.n_mips[k] = len(ts)
+            c.width[k], c.height[k] = w, h
+            c.shift[k][0], c.shift[k][1] = self.shift[k]
+            for m, t in enumerate(ts):
+                c.data[k][m] = t.data_ptr()
+        self.c = c
+
+    @property
+    def n_levels(self) -> int:
+        return len(self.tensors)
+
+
+def decode_filtered(lat: LatentMips, mlp: Mlp, uv: torch.Tensor, duv: torch.Tensor, filter: str = "trilinear",
+                    max_aniso: int = 16, packed: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                    out_dtype=torch.float32) -> torch.Tensor:
+    """FP16 matrix-core decode with trilinear or anisotropic filtering of the
+    latents over their mip chains; duv [n][4] = (du/dx, dv/dx, du/dy, dv/dy)."""
+    _require_cuda(uv, "uv")
+    _require_cuda(duv, "duv")
+    n = uv.shape[0]
+    if uv.dim() != 2 or uv.shape[1] != 2 or uv.dtype != torch.float32 or not uv.is_contiguous():
+        raise ValueError("uv must be contiguous float32 [n][2]")
+    if tuple(duv.shape) != (n, 4) or duv.dtype != torch.float32 or not duv.is_contiguous():
+        raise ValueError("duv must be contiguous float32 [n][4]")
+    if packed is None:
+        packed = pack(mlp, "f16")
+    if out is None:
+        out = torch.empty((n, mlp.n_out), dtype=out_dtype, device=uv.device)
+    check(A.lib().ntc_decode_filtered(ctypes.byref(lat.c), ctypes.byref(mlp.c), _ptr(packed), _ptr(uv), _ptr(duv), n,
+                                      _ptr(out), OUT_DTYPES[out.dtype], FILTERS[filter], max_aniso,
+                                      _stream_handle()))
+    return out

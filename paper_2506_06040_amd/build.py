@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libntc.so")
 SOURCES = ["ntc_api.hip", "ntc_plain.hip", "ntc_mfma.hip", "ntc_backward.hip", "ntc_batched.hip", "ntc_qat.hip",
-           "ntc_classify.hip"]
+           "ntc_classify.hip", "ntc_filtered.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

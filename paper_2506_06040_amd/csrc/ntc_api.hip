@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -283,6 +284,79 @@ ntc_status ntc_bc1_decode_texels(const ntc_latents *lat, int32_t level, float *o
   const LatArgs a = to_lat_args(lat);
   hipError_t e = launch_bc1_texels(a.lv[level], out, numer, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "texel launch");
+  return ok();
+}
+
+ntc_status ntc_decode_filtered(const ntc_latent_mips *lat, const ntc_mlp *mlp, const void *packed, const float *uv,
+                               const float *duv, int64_t n, void *out, int32_t out_dtype, int32_t filter,
+                               int32_t max_aniso, void *stream) {
+  if (!lat) return fail(NTC_E_NULL, "latents is NULL");
+  if (lat->n_levels < 1 || lat->n_levels > NTC_MAX_LEVELS)
+    return fail(NTC_E_SHAPE, "n_levels %d outside 1..%d", lat->n_levels, NTC_MAX_LEVELS);
+  MlpShape s;
+  ntc_status st = check_mlp_shape(mlp, lat->n_levels, &s);
+  if (st) return st;
+  if (s.n_layers > 4) return fail(NTC_E_UNSUPPORTED, "filtered decode supports at most 4 layers");
+  if (filter != NTC_FILTER_TRILINEAR && filter != NTC_FILTER_ANISOTROPIC)
+    return fail(NTC_E_UNSUPPORTED, "filter %d", filter);
+  if (max_aniso < 1 || max_aniso > NTC_MAX_ANISO) return fail(NTC_E_SHAPE, "max_aniso %d outside 1..%d", max_aniso, NTC_MAX_ANISO);
+  if (out_dtype != NTC_F32 && out_dtype != NTC_F16) return fail(NTC_E_UNSUPPORTED, "out dtype %d", out_dtype);
+  if (n < 0 || n > ((int64_t)1 << 40)) return fail(NTC_E_SHAPE, "n %lld outside 0..2^40", (long long)n);
+  for (int k = 0; k < lat->n_levels; ++k) {
+    const int w = lat->width[k], h = lat->height[k], nm = lat->n_mips[k];
+    if (nm < 1 || nm > NTC_MAX_MIPS) return fail(NTC_E_SHAPE, "level %d: n_mips %d outside 1..%d", k, nm, NTC_MAX_MIPS);
+    if (w < 4 || h < 4 || w > 65536 || h > 65536)
+      return fail(NTC_E_SHAPE, "level %d: %d x %d outside 4..65536", k, w, h);
+    for (int m = 0; m < nm; ++m) {
+      if (((w >> m) & 3) || ((h >> m) & 3) || (w >> m) < 4 || (h >> m) < 4 || ((w >> m) << m) != w ||
+          ((h >> m) << m) != h)
+        return fail(NTC_E_SHAPE, "level %d mip %d: %d x %d is not a multiple of 4 of at least 4", k, m, w >> m,
+                    h >> m);
+      if (!lat->data[k][m]) return fail(NTC_E_NULL, "level %d mip %d has no data", k, m);
+      if (!aligned(lat->data[k][m], 8)) return fail(NTC_E_ALIGN, "level %d mip %d misaligned", k, m);
+    }
+    if (!(fabsf(lat->shift[k][0]) <= 1.0f) || !(fabsf(lat->shift[k][1]) <= 1.0f))
+      return fail(NTC_E_SHAPE, "level %d: |shift| > 1", k);
+  }
+  if (n == 0) return ok();
+  if (!packed || !uv || !duv || !out) return fail(NTC_E_NULL, "packed, uv, duv or out is NULL");
+  if (!aligned(packed, 256) || !aligned(uv, 8) || !aligned(duv, 16) || !aligned(out, 16))
+    return fail(NTC_E_ALIGN, "misaligned packed, uv, duv or out");
+  FilterArgs f;
+  memset(&f, 0, sizeof f);
+  DecodeArgs &a = f.d;
+  a.packed = (const uint8_t *)packed;
+  a.uv = (const float2 *)uv;
+  a.out = out;
+  a.n = n;
+  a.n_tiles = (n + 63) / 64;
+  a.n_out = s.n_out;
+  a.out_f16 = out_dtype == NTC_F16;
+  a.n_layers = s.n_layers;
+  a.lay = pack_layout(s, NTC_F16);
+  f.duv = (const float4 *)duv;
+  f.n_levels = lat->n_levels;
+  f.filter = filter;
+  f.max_aniso = max_aniso;
+  for (int k = 0; k < NTC_MAX_LEVELS; ++k) {
+    // unused levels and mips mirror valid ones so that every pointer stays valid
+    const int src = k < lat->n_levels ? k : 0;
+    f.n_mips[k] = lat->n_mips[src];
+    f.w0[k] = (float)lat->width[src];
+    f.h0[k] = (float)lat->height[src];
+    f.sx[k] = lat->shift[src][0];
+    f.sy[k] = lat->shift[src][1];
+    for (int m = 0; m < kMaxMips; ++m) {
+      const int ms = m < lat->n_mips[src] ? m : lat->n_mips[src] - 1;
+      MipArgs &M = f.mip[k][m];
+      M.bc1 = (const uint2 *)lat->data[src][ms];
+      M.w = lat->width[src] >> ms;
+      M.h = lat->height[src] >> ms;
+      M.bw = M.w / 4;
+    }
+  }
+  hipError_t e = launch_decode_filtered(f, s, device_cus() * 8, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "filtered decode launch");
   return ok();
 }
 

@@ -161,4 +161,22 @@ hipError_t launch_gather_uv(const float *uv_image, const int32_t *list, int64_t 
 hipError_t launch_scatter_rows(const void *rows, const int32_t *list, int64_t n, int c, int elem_bytes, void *image,
                                hipStream_t st);
 
+// Filtered decode over mip chains (ntc_filtered.hip).
+constexpr int kMaxMips = 12;
+constexpr int kMaxAniso = 16;
+struct MipArgs {
+  const uint2 *bc1;
+  int32_t w, h, bw, pad_;
+};
+struct FilterArgs {
+  DecodeArgs d;            // packed image, uv, out, n, shapes (d.lat is unused)
+  const float4 *duv;       // [n]: du/dx, dv/dx, du/dy, dv/dy
+  MipArgs mip[kMaxLevels][kMaxMips];
+  int32_t n_mips[kMaxLevels];
+  float w0[kMaxLevels], h0[kMaxLevels];  // mip 0 sizes
+  float sx[kMaxLevels], sy[kMaxLevels];  // shifts in texels of each mip
+  int32_t n_levels, filter, max_aniso, pad_;
+};
+hipError_t launch_decode_filtered(const FilterArgs &f, const MlpShape &s, int grid_waves, hipStream_t st);
+
 }  // namespace ntc

@@ -1,0 +1,80 @@
+"""Filtered decode over BC1 mip chains (ntc_decode_filtered; Sec. 3.2 mip
+chains, Sec. 3.3 trilinear / anisotropic fetches) against the FP64 oracle
+(oracle/filtering.py). The tap count N is an integer both sides decide with
+the same FP32 operations; everything else is continuous in the inputs and
+held to the FP16 gate."""
+import numpy as np
+import pytest
+import torch
+
+import ntc_inputs as I
+import oracle as O
+from oracle import filtering as F
+
+pytestmark = pytest.mark.gpu
+
+TOL_F16_ABS = 2e-3
+
+
+def _ntc():
+    import paper_2506_06040_amd as ntc
+    return ntc
+
+
+def _case(seed, sizes, dims=(14, 64, 64, 64, 8)):
+    rng = np.random.default_rng(seed)
+    chains = [I.bc1_mip_chain(rng, w, h) for (w, h) in sizes]
+    Ws, bs = I.xavier_mlp(rng, dims, bias="normal")
+    return rng, chains, Ws, bs
+
+
+def test_zero_derivatives_equal_bilinear_decode():
+    ntc = _ntc()
+    rng, chains, Ws, bs = _case(1, [(64, 64), (32, 32), (16, 16), (8, 8)])
+    uv = rng.random((5000, 2)).astype(np.float32)
+    mlp = ntc.Mlp(Ws, bs)
+    lm = ntc.LatentMips(chains, shift=I.PAPER_SHIFT)
+    uvt = torch.from_numpy(uv).cuda()
+    zero = torch.zeros((uv.shape[0], 4), device="cuda")
+    ref = ntc.decode(ntc.Latents([c[0] for c in chains], shift=I.PAPER_SHIFT), mlp, uvt, compute="f16")
+    for filt in ("trilinear", "anisotropic"):
+        got = ntc.decode_filtered(lm, mlp, uvt, zero, filter=filt)
+        assert torch.equal(got, ref), filt
+
+
+@pytest.mark.parametrize("filt,max_aniso", [("trilinear", 16), ("anisotropic", 16), ("anisotropic", 4)])
+def test_perspective_plane_parity(filt, max_aniso):
+    ntc = _ntc()
+    sizes = [(256, 256), (128, 128), (64, 64), (32, 32)]
+    rng, chains, Ws, bs = _case(2, sizes)
+    uv, duv = I.perspective_plane(160, 96, far=24.0)
+    # the plane seen at 4x the latent texel density: level 0 spans 0.1 .. 5 texels per pixel
+    duv = duv * np.float32(0.625 * 4)
+    out = ntc.decode_filtered(ntc.LatentMips(chains, shift=I.PAPER_SHIFT), ntc.Mlp(Ws, bs),
+                              torch.from_numpy(uv).cuda(), torch.from_numpy(duv).cuda(), filter=filt,
+                              max_aniso=max_aniso).cpu().numpy()
+    ref = F.decode(chains, I.PAPER_SHIFT, O.Mlp(Ws, bs), uv, duv, filt, max_aniso)
+    err = np.abs(out - ref).max()
+    px2, py2 = F.axes_sq_f32(duv, 256, 256)
+    n = F.aniso_count(px2, py2, max_aniso)
+    print(f"\n[filtered {filt} {max_aniso}] n={uv.shape[0]} taps {np.bincount(n)} max err {err:.2e}", flush=True)
+    assert err <= TOL_F16_ABS
+
+
+def test_random_derivatives_parity():
+    ntc = _ntc()
+    rng, chains, Ws, bs = _case(3, [(128, 64), (64, 32), (32, 16), (16, 8)], dims=(14, 32, 32, 8))
+    n = 3001
+    uv = (rng.random((n, 2)) * 1.2 - 0.1).astype(np.float32)
+    duv = (rng.standard_normal((n, 4)) * np.exp(rng.uniform(-8, 1, (n, 1)))).astype(np.float32)
+    duv[:50] = 0.0
+    duv[50:100, 2:] = 0.0           # degenerate footprint: one axis of length 0
+    duv[100:150] *= 1e4             # far beyond the last mip
+    for filt in ("trilinear", "anisotropic"):
+        out = ntc.decode_filtered(ntc.LatentMips(chains, shift=I.PAPER_SHIFT), ntc.Mlp(Ws, bs),
+                                  torch.from_numpy(uv).cuda(), torch.from_numpy(duv).cuda(), filter=filt,
+                                  max_aniso=8).cpu().numpy()
+        ref = F.decode(chains, I.PAPER_SHIFT, O.Mlp(Ws, bs), uv, duv, filt, 8)
+        err = np.abs(out - ref).max()
+        print(f"[random duv {filt}] max err {err:.2e}", flush=True)
+        assert err <= TOL_F16_ABS, filt
