@@ -316,8 +316,7 @@ def main():
         mat_ids = torch.from_numpy(I.material_frame(np.random.default_rng(7), fw, fh, len(mats),
                                                     noise=0.002)).to(dev)
         uv_img = torch.from_numpy(I.pixel_uv(fw, fh)).to(dev)
-        fd = ntc.FrameDecoder([(m.lat, m.mlp) for m in mats], cfg=ntc.batch_cfg(
-            n_cus=ntc.api._device_cus(dev), **best))
+        fd = ntc.FrameDecoder([(m.lat, m.mlp) for m in mats])
         fp = fd.plan(mat_ids, uv_img)
         n_valid = int(fp["pixel_list"].shape[0])
         A = ntc.api.A

@@ -482,7 +482,16 @@ class FrameDecoder:
             a, b = offs[m], offs[m + 1]
             if b > a:
                 mats.append(Material(lat, mlp, uv[a:b], out=rows[a:b], packed=self.packed[m]))
-        plan = BatchPlan(mats, self.cfg, device=self.device) if mats else None
+        cfg = self.cfg
+        if cfg is None and mats:
+            # about two work items per persistent wave: a frame's materials
+            # cover very different pixel counts, and longest-first packing
+            # balances only when items outnumber waves
+            n_cus = _device_cus(self.device)
+            waves = n_cus * 8
+            item = int(min(65536, max(64, (lst.shape[0] // (2 * waves)) // 64 * 64)))
+            cfg = batch_cfg(item_pixels=item, waves_per_cu=8, n_cus=n_cus)
+        plan = BatchPlan(mats, cfg, device=self.device) if mats else None
         return dict(pixel_list=lst, mat_offsets=off, mat_simple=simple, tile_class=tcls, uv=uv, rows=rows,
                     plan=plan, materials=mats)
 
