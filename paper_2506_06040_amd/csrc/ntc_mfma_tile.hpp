@@ -56,6 +56,9 @@
 #else
 #define NTC_UNROLL_STAGED NTC_PRAGMA(unroll 1)
 #endif
+#ifndef NTC_MLP_PRIO  // wave priority (0..3) while a wave runs its MLP
+#define NTC_MLP_PRIO 2
+#endif
 #ifndef NTC_STORE_AUX  // cache policy of the output stores (2: non-temporal)
 #define NTC_STORE_AUX 2
 #endif
@@ -952,6 +955,10 @@ __device__ __forceinline__ void subspan_mlp(const DecodeArgs &a, const MfmaWeigh
                                             __amdgpu_buffer_rsrc_t ors, const typename P::Frag (&bx)[2], int q,
                                             int salt) {
   using Frag = typename P::Frag;
+  // The other wave of the SIMD is usually sampling (vector work): issuing
+  // this wave's matrix chain first lets the two overlap instead of both
+  // waves reaching the MLP together.
+  __builtin_amdgcn_s_setprio(NTC_MLP_PRIO);
   // both N-tiles in one MLP pass when the weights leave room for two sets of
   // accumulators, otherwise one after the other
   if constexpr (HID >= 64 && NL >= 3 && NTC_WIDE_NT == 1) {
@@ -961,6 +968,7 @@ __device__ __forceinline__ void subspan_mlp(const DecodeArgs &a, const MfmaWeigh
   } else {
     mlp_store<P, HID, NL, 2, VEC4, UNIT>(a, W, bias, ors, bx, 2 * q, salt);
   }
+  __builtin_amdgcn_s_setprio(0);
 }
 
 // Output resource of a span: stores past `span` pixels are dropped.
