@@ -139,3 +139,76 @@ def test_backward_and_texel_validation(A):
     assert L.ntc_bc1_decode_texels(ctypes.byref(lat_b), 4, 0x1000, None, None) == A.E_SHAPE
     assert L.ntc_bc1_decode_texels(ctypes.byref(lat_b), 0, None, None, None) == A.E_NULL
     assert L.ntc_bc1_decode_texels(ctypes.byref(lat_f), 0, 0x1000, None, None) == A.E_UNSUPPORTED
+
+
+def test_qat_validation(A):
+    L = A.lib()
+    p = 0x1000
+    assert L.ntc_qat_texels(None, 16, 16, p, None) == A.E_NULL
+    assert L.ntc_qat_texels(p, 16, 16, None, None) == A.E_NULL
+    assert L.ntc_qat_texels(p, 18, 16, p, None) == A.E_SHAPE      # not a multiple of 4
+    assert L.ntc_qat_texels(p, 0, 16, p, None) == A.E_SHAPE
+    assert L.ntc_qat_texels(p, 16, 32768, p, None) == A.E_SHAPE   # above 16384
+    assert L.ntc_qat_texels(p + 2, 16, 16, p, None) == A.E_ALIGN
+    assert L.ntc_qat_backward(p, 16, 16, None, p, None) == A.E_NULL
+    assert L.ntc_qat_export_bc1(p, 16, 16, p + 4, None) == A.E_ALIGN
+    assert L.ntc_qat_export_bc1(p, 16, 12, None, None) == A.E_NULL
+
+
+def test_classify_validation(A):
+    L = A.lib()
+    p = 0x1000
+    n = ctypes.c_size_t(0)
+    assert L.ntc_classify_workspace(64, 32, 3, ctypes.byref(n)) == A.OK and n.value > 0
+    assert L.ntc_classify_workspace(64, 32, 3, None) == A.E_NULL
+    assert L.ntc_classify_workspace(0, 32, 3, ctypes.byref(n)) == A.E_SHAPE
+    assert L.ntc_classify_workspace(64, 32, 0, ctypes.byref(n)) == A.E_SHAPE
+    assert L.ntc_classify_workspace(64, 32, 5000, ctypes.byref(n)) == A.E_SHAPE
+    assert L.ntc_classify_workspace(40000, 32, 3, ctypes.byref(n)) == A.E_SHAPE
+    need = n.value
+    assert L.ntc_classify(p, 64, 32, 3, p, p, p, None, p, need - 1, None) == A.E_WORKSPACE
+    assert L.ntc_classify(None, 64, 32, 3, p, p, p, None, p, need, None) == A.E_NULL
+    assert L.ntc_classify(p, 64, 32, 3, p, p, p, None, p + 64, need, None) == A.E_ALIGN
+    assert L.ntc_gather_uv(p, p, -1, p, None) == A.E_SHAPE
+    assert L.ntc_gather_uv(None, p, 0, None, None) == A.OK     # nothing to do
+    assert L.ntc_gather_uv(None, p, 10, p, None) == A.E_NULL
+    assert L.ntc_scatter_rows(p, p, 10, 17, A.F32, p, None) == A.E_SHAPE
+    assert L.ntc_scatter_rows(p, p, 10, 8, A.FP8_E4M3, p, None) == A.E_UNSUPPORTED
+    assert L.ntc_scatter_rows(p + 2, p, 10, 8, A.F32, p, None) == A.E_ALIGN
+
+
+def test_filtered_validation(A):
+    L = A.lib()
+    mlp = A.ntc_mlp()
+    mlp.n_layers = 3
+    for i, d in enumerate((14, 32, 32, 8)):
+        mlp.dims[i] = d
+    lat = A.ntc_latent_mips()
+    lat.n_levels = 4
+    for k, s in enumerate((64, 32, 16, 8)):
+        lat.width[k] = lat.height[k] = s
+        lat.n_mips[k] = 2
+        for m in range(2):
+            lat.data[k][m] = 0x1000
+    p = 0x1000
+
+    def call(n=100, filt=A.FILTER_TRILINEAR, aniso=16, uv=p, duv=p, out=p, packed=p):
+        return L.ntc_decode_filtered(ctypes.byref(lat), ctypes.byref(mlp), packed, uv, duv, n, out, A.F32, filt,
+                                     aniso, None)
+
+    assert L.ntc_decode_filtered(None, ctypes.byref(mlp), p, p, p, 10, p, A.F32, 1, 16, None) == A.E_NULL
+    assert call(filt=3) == A.E_UNSUPPORTED
+    assert call(aniso=0) == A.E_SHAPE and call(aniso=17) == A.E_SHAPE
+    assert call(duv=None) == A.E_NULL
+    assert call(duv=p + 8) == A.E_ALIGN
+    assert call(n=-1) == A.E_SHAPE
+    assert call(n=0, uv=None, duv=None, out=None, packed=None) == A.OK
+    lat.n_mips[3] = 3   # 8 >> 2 = 2 texels: too small
+    lat.data[3][2] = p
+    assert call() == A.E_SHAPE
+    lat.n_mips[3] = 2
+    lat.data[2][1] = 0
+    assert call() == A.E_NULL
+    lat.data[2][1] = p
+    lat.shift[0][0] = 2.0
+    assert call() == A.E_SHAPE
