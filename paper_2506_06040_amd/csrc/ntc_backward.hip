@@ -92,8 +92,19 @@ __device__ __forceinline__ void accum_outer(const float *D, int ds, const float 
   }
 }
 
+// Weights and biases of the layers, each as its own read-only, non-aliasing
+// kernel argument: their loads are uniform and no store of the kernel can
+// reach them, so the compiler reads them through the scalar cache once per
+// wavefront instead of once per lane.
 template <int HID, int NL>
-__global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a) {
+__global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a, const float *__restrict__ W0,
+                                                      const float *__restrict__ W1, const float *__restrict__ W2,
+                                                      const float *__restrict__ W3, const float *__restrict__ b0,
+                                                      const float *__restrict__ b1, const float *__restrict__ b2,
+                                                      const float *__restrict__ b3) {
+  // layer l's parameters (l is a constant wherever this is called)
+  auto Wl = [&](int l) { return l == 0 ? W0 : (l == 1 ? W1 : (l == 2 ? W2 : W3)); };
+  auto bl = [&](int l) { return l == 0 ? b0 : (l == 1 ? b1 : (l == 2 ? b2 : b3)); };
   using Dm = BwdDims<HID, NL>;
   extern __shared__ float smem[];
   // LDS: per-layer padded accumulators (W then b), then the D / A staging.
@@ -146,8 +157,8 @@ __global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a) {
     }
     float h[NL - 1][HID];
     {
-      const float *W = a.W[0];
-      const float *b = a.b[0];
+      const float *W = Wl(0);
+      const float *b = bl(0);
       const int in0 = a.dims[0];
 #pragma unroll
       for (int o = 0; o < HID; ++o) {
@@ -160,8 +171,8 @@ __global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a) {
     }
 #pragma unroll
     for (int l = 1; l < NL - 1; ++l) {
-      const float *W = a.W[l];
-      const float *b = a.b[l];
+      const float *W = Wl(l);
+      const float *b = bl(l);
 #pragma unroll
       for (int o = 0; o < HID; ++o) {
         float z = b[o];
@@ -172,8 +183,8 @@ __global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a) {
     }
     float d[HID > 16 ? HID : 16];
     {
-      const float *W = a.W[NL - 1];
-      const float *b = a.b[NL - 1];
+      const float *W = Wl(NL - 1);
+      const float *b = bl(NL - 1);
 #pragma unroll
       for (int o = 0; o < 16; ++o) {
         d[o] = 0.f;
@@ -217,7 +228,7 @@ __global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a) {
       (void)K;
       if (l > 0) {
         // D_{l-1} = (W_l^T D_l) * [A_l > 0]
-        const float *W = a.W[l];
+        const float *W = Wl(l);
         const int rows = (l == NL - 1) ? n_out : HID;
         float nd[HID];
 #pragma unroll
@@ -235,7 +246,7 @@ __global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a) {
         for (int k = HID; k < (HID > 16 ? HID : 16); ++k) d[k] = 0.f;
       } else if (valid) {
         // dx = W_0^T D_0, spread onto the taps of every level
-        const float *W = a.W[0];
+        const float *W = Wl(0);
         const int in0 = a.dims[0];
         float dx[12];
 #pragma unroll
@@ -332,7 +343,8 @@ template <int HID, int NL>
 static hipError_t launch_bwd(const BackwardArgs &a, hipStream_t st) {
   const size_t lds = bwd_lds_bytes<HID, NL>();
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((backward_kernel<HID, NL>), dim3(a.n_blocks), dim3(64), lds, st, a);
+  hipLaunchKernelGGL((backward_kernel<HID, NL>), dim3(a.n_blocks), dim3(64), lds, st, a, a.W[0], a.W[1], a.W[2],
+                     a.W[3], a.b[0], a.b[1], a.b[2], a.b[3]);
   return hipGetLastError();
 }
 

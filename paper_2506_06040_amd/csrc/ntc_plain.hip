@@ -333,8 +333,12 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 template <int HID, bool CALIB>
-__global__ __launch_bounds__(256) void decode_plain_kernel(DecodeArgs a, float *__restrict__ amax) {
-  const float *__restrict__ wp = reinterpret_cast<const float *>(a.packed);
+// The packed image comes as its own read-only, non-aliasing argument: its
+// loads are then uniform and unclobbered, and the compiler reads the weights
+// through the scalar cache (one load for the whole wavefront) instead of
+// once per lane.
+__global__ __launch_bounds__(256) void decode_plain_kernel(DecodeArgs a, const float *__restrict__ wp,
+                                                           float *__restrict__ amax) {
   const int n_levels = a.lat.n_levels;
   const int n_layers = a.n_layers;
   const int n_out = a.n_out;
@@ -435,9 +439,11 @@ static hipError_t launch_plain_hid(const DecodeArgs &a, float *calib, int n_cus,
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   if (calib)
-    hipLaunchKernelGGL((decode_plain_kernel<HID, true>), dim3((unsigned)blocks), dim3(bs), 0, st, a, calib);
+    hipLaunchKernelGGL((decode_plain_kernel<HID, true>), dim3((unsigned)blocks), dim3(bs), 0, st, a,
+                       reinterpret_cast<const float *>(a.packed), calib);
   else
-    hipLaunchKernelGGL((decode_plain_kernel<HID, false>), dim3((unsigned)blocks), dim3(bs), 0, st, a, calib);
+    hipLaunchKernelGGL((decode_plain_kernel<HID, false>), dim3((unsigned)blocks), dim3(bs), 0, st, a,
+                       reinterpret_cast<const float *>(a.packed), calib);
   return hipGetLastError();
 }
 
