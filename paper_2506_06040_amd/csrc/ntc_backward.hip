@@ -24,7 +24,11 @@ namespace ntc {
 // Persistent workgroups of the backward (two per compute unit of a 256-CU
 // part; fewer for small batches). Depends on n only, so the workspace size
 // is known on the host without a device query.
-constexpr int kBwdMaxBlocks = 512;
+constexpr int kBwdMaxBlocks = 1024;
+// Samples staged in LDS per round of the dW accumulation (a chunk of 64 takes
+// 64 / kBwdStage rounds): with 16, a workgroup needs under 40 KB of LDS and
+// four fit on a compute unit, one per SIMD.
+constexpr int kBwdStage = 16;
 
 // Number of MLP parameters, laid out per layer as W_l [rows][cols] then b_l.
 static inline int n_params_of(const MlpShape &s) {
@@ -54,7 +58,7 @@ struct BwdDims {
   static constexpr int out(int l) { return l == NL - 1 ? 16 : HID; }
 };
 
-// Accumulate D^T A over the 64 samples of the chunk into acc (row-major
+// Accumulate D^T A over the kBwdStage staged samples into acc (row-major
 // [M][K] weights of the padded layer) and column sums of D into accb [M].
 // Lane (a, b) = (lane / 8, lane % 8) owns rows [a BM, a BM + BM) and columns
 // [b BK, b BK + BK) with BM = M / 8, BK = K / 8.
@@ -71,7 +75,7 @@ __device__ __forceinline__ void accum_outer(const float *D, int ds, const float 
 #pragma unroll
     for (int j = 0; j < BK; ++j) w[i][j] = 0.f;
   }
-  for (int s = 0; s < 64; ++s) {
+  for (int s = 0; s < kBwdStage; ++s) {
     float dv[BM], av[BK];
 #pragma unroll
     for (int i = 0; i < BM; ++i) dv[i] = D[s * ds + a * BM + i];
@@ -119,9 +123,9 @@ __global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a, const floa
     tot += Dm::out(l);
   }
   float *acc = smem;
-  float *Dst = smem + tot;        // [64][dstride]
+  float *Dst = smem + tot;        // [kBwdStage][dstride]
   constexpr int dstride = (HID > 16 ? HID : 16) + 4;
-  float *Ast = Dst + 64 * dstride;  // [64][astride]
+  float *Ast = Dst + kBwdStage * dstride;  // [kBwdStage][astride]
   constexpr int astride = (HID > 16 ? HID : 16) + 4;
   (void)kStageD;
 
@@ -205,25 +209,31 @@ __global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a, const floa
       constexpr int dummy = 0;
       (void)dummy;
       const int M = Dm::out(l), K = Dm::in(l);
-      // stage D_l and A_l of this lane's sample
+      // stage D_l and A_l of the chunk's samples, kBwdStage per round, and
+      // accumulate their outer products
+      for (int r = 0; r < 64 / kBwdStage; ++r) {
+        if ((lane / kBwdStage) == r) {
+          const int row = lane % kBwdStage;
 #pragma unroll
-      for (int o = 0; o < (l == NL - 1 ? 16 : HID); ++o) Dst[lane * dstride + o] = d[o];
-      if (l == 0) {
+          for (int o = 0; o < (l == NL - 1 ? 16 : HID); ++o) Dst[row * dstride + o] = d[o];
+          if (l == 0) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) Ast[lane * astride + k] = x[k];
-      } else {
+            for (int k = 0; k < 16; ++k) Ast[row * astride + k] = x[k];
+          } else {
 #pragma unroll
-        for (int k = 0; k < HID; ++k) Ast[lane * astride + k] = h[l - 1][k];
+            for (int k = 0; k < HID; ++k) Ast[row * astride + k] = h[l - 1][k];
+          }
+        }
+        __syncthreads();
+        if (l == NL - 1) {
+          accum_outer<16, HID>(Dst, dstride, Ast, astride, acc + acc_off[l], acc + accb_off[l], lane);
+        } else if (l == 0) {
+          accum_outer<HID, 16>(Dst, dstride, Ast, astride, acc + acc_off[l], acc + accb_off[l], lane);
+        } else {
+          accum_outer<HID, HID>(Dst, dstride, Ast, astride, acc + acc_off[l], acc + accb_off[l], lane);
+        }
+        __syncthreads();
       }
-      __syncthreads();
-      if (l == NL - 1) {
-        accum_outer<16, HID>(Dst, dstride, Ast, astride, acc + acc_off[l], acc + accb_off[l], lane);
-      } else if (l == 0) {
-        accum_outer<HID, 16>(Dst, dstride, Ast, astride, acc + acc_off[l], acc + accb_off[l], lane);
-      } else {
-        accum_outer<HID, HID>(Dst, dstride, Ast, astride, acc + acc_off[l], acc + accb_off[l], lane);
-      }
-      __syncthreads();
       (void)M;
       (void)K;
       if (l > 0) {
@@ -336,7 +346,7 @@ static size_t bwd_lds_bytes() {
   int tot = 0;
   for (int l = 0; l < NL; ++l) tot += Dm::out(l) * Dm::in(l) + Dm::out(l);
   const int stride = (HID > 16 ? HID : 16) + 4;
-  return (size_t)(tot + 2 * 64 * stride) * sizeof(float);
+  return (size_t)(tot + 2 * kBwdStage * stride) * sizeof(float);
 }
 
 template <int HID, int NL>
