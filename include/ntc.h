@@ -312,11 +312,20 @@ typedef struct {
     ntc_latents lat;   /* BC1 latents [device] */
     ntc_mlp mlp;       /* shapes (dims, n_layers); W / b may be NULL */
     const void *packed;/* NTC_F16 packed image of this material [device] */
-    const float *uv;   /* [n][2] [device] */
+    const float *uv;   /* [n][2] [device] (with pixel_index: the uv image, [image_pixels][2]) */
     int64_t n;
-    void *out;         /* [n][C] [device] */
+    void *out;         /* [n][C] [device] (with pixel_index: the output image, [image_pixels][C]) */
     int32_t out_dtype; /* NTC_F32 or NTC_F16 */
     int32_t reserved;
+    /* Optional [device] int32 [n]: sample s is pixel pixel_index[s] of images
+     * of image_pixels pixels: its uv is read from uv[pixel_index[s]] and its
+     * output written to out[pixel_index[s]] (the per-material lists of
+     * ntc_classify feed the decode directly). An index outside
+     * 0..image_pixels-1 reads uv (0, 0) and writes nothing. NULL: uv and out
+     * are the material's own [n] arrays. image_pixels * C * (4 or 2) must be
+     * below 2^31. */
+    const int32_t *pixel_index;
+    int64_t image_pixels;
 } ntc_material;
 
 /* Batch options. item_pixels: pixels per work item (multiple of 64,

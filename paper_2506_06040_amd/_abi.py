@@ -52,7 +52,8 @@ class ntc_tile_cfg(ctypes.Structure):
 class ntc_material(ctypes.Structure):
     _fields_ = [("lat", ntc_latents), ("mlp", ntc_mlp), ("packed", ctypes.c_void_p),
                 ("uv", ctypes.c_void_p), ("n", ctypes.c_int64), ("out", ctypes.c_void_p),
-                ("out_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("out_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("pixel_index", ctypes.c_void_p), ("image_pixels", ctypes.c_int64)]
 
 
 class ntc_batch_cfg(ctypes.Structure):

@@ -348,12 +348,16 @@ def qat_texels_fn(params: torch.Tensor, width: int, height: int) -> torch.Tensor
 # ---------------------------------------------------------------------------
 class Material:
     """One material of a batch: BC1 latents, its MLP (FP16 image packed on
-    construction), its uv and an output buffer."""
+    construction), its uv and an output buffer. With pixel_index (int32 [n]),
+    uv and out are whole images ([P][2], [P][C]) and sample s is pixel
+    pixel_index[s] of them."""
 
     def __init__(self, lat: Latents, mlp: Mlp, uv: torch.Tensor, out: Optional[torch.Tensor] = None,
-                 out_dtype=torch.float32, packed: Optional[torch.Tensor] = None):
+                 out_dtype=torch.float32, packed: Optional[torch.Tensor] = None,
+                 pixel_index: Optional[torch.Tensor] = None):
         _require_cuda(uv, "uv")
         self.lat, self.mlp, self.uv = lat, mlp, uv
+        self.pixel_index = pixel_index
         self.packed = packed if packed is not None else pack(mlp, "f16")
         self.out = out if out is not None else torch.empty((uv.shape[0], mlp.n_out), dtype=out_dtype,
                                                            device=uv.device)
@@ -362,10 +366,19 @@ class Material:
         c.mlp = mlp.c
         c.packed = self.packed.data_ptr()
         c.uv = uv.data_ptr()
-        c.n = uv.shape[0]
         c.out = self.out.data_ptr()
         c.out_dtype = OUT_DTYPES[self.out.dtype]
         c.reserved = 0
+        if pixel_index is None:
+            c.n = uv.shape[0]
+            c.pixel_index = None
+            c.image_pixels = 0
+        else:
+            if pixel_index.dtype != torch.int32 or not pixel_index.is_contiguous():
+                raise ValueError("pixel_index must be contiguous int32")
+            c.n = pixel_index.shape[0]
+            c.pixel_index = pixel_index.data_ptr()
+            c.image_pixels = uv.numel() // 2
         self.c = c
 
 
@@ -471,17 +484,32 @@ class FrameDecoder:
         self.packed = [pack(m, "f16") for _, m in self.materials]
         self.cfg, self.out_dtype, self.device = cfg, out_dtype, device
 
-    def plan(self, mat_ids: torch.Tensor, uv_image: torch.Tensor):
-        """Classification, gathered uv and the batch plan of one frame."""
+    def plan(self, mat_ids: torch.Tensor, uv_image: torch.Tensor, out: Optional[torch.Tensor] = None,
+             indexed: bool = True):
+        """Classification and the batch plan of one frame. indexed: the
+        decode reads uv from uv_image and writes `out` ([H][W][C]) through
+        the pixel lists; otherwise uv is gathered into per-material arrays
+        and the rows are decoded into a separate buffer (to be scattered)."""
         lst, off, simple, tcls = classify(mat_ids, len(self.materials))
-        uv = gather_uv(uv_image, lst)
-        rows = torch.empty((lst.shape[0], self.n_out), dtype=self.out_dtype, device=self.device)
         offs = off.cpu().tolist()
         mats = []
-        for m, (lat, mlp) in enumerate(self.materials):
-            a, b = offs[m], offs[m + 1]
-            if b > a:
-                mats.append(Material(lat, mlp, uv[a:b], out=rows[a:b], packed=self.packed[m]))
+        if indexed:
+            if out is None:
+                out = torch.zeros((mat_ids.shape[0], mat_ids.shape[1], self.n_out), dtype=self.out_dtype,
+                                  device=self.device)
+            uv = uv_image.reshape(-1, 2)
+            rows = out.reshape(-1, self.n_out)
+            for m, (lat, mlp) in enumerate(self.materials):
+                a, b = offs[m], offs[m + 1]
+                if b > a:
+                    mats.append(Material(lat, mlp, uv, out=rows, packed=self.packed[m], pixel_index=lst[a:b]))
+        else:
+            uv = gather_uv(uv_image, lst)
+            rows = torch.empty((lst.shape[0], self.n_out), dtype=self.out_dtype, device=self.device)
+            for m, (lat, mlp) in enumerate(self.materials):
+                a, b = offs[m], offs[m + 1]
+                if b > a:
+                    mats.append(Material(lat, mlp, uv[a:b], out=rows[a:b], packed=self.packed[m]))
         cfg = self.cfg
         if cfg is None and mats:
             # about two work items per persistent wave: a frame's materials
@@ -493,18 +521,22 @@ class FrameDecoder:
             cfg = batch_cfg(item_pixels=item, waves_per_cu=8, n_cus=n_cus)
         plan = BatchPlan(mats, cfg, device=self.device) if mats else None
         return dict(pixel_list=lst, mat_offsets=off, mat_simple=simple, tile_class=tcls, uv=uv, rows=rows,
-                    plan=plan, materials=mats)
+                    plan=plan, materials=mats, indexed=indexed)
 
-    def decode(self, mat_ids: torch.Tensor, uv_image: torch.Tensor, out: Optional[torch.Tensor] = None):
+    def decode(self, mat_ids: torch.Tensor, uv_image: torch.Tensor, out: Optional[torch.Tensor] = None,
+               indexed: bool = True):
         """Output image [H][W][C]; pixels without a neural material keep the
         value of `out` (zero when it is not given)."""
         h, w = mat_ids.shape
         if out is None:
             out = torch.zeros((h, w, self.n_out), dtype=self.out_dtype, device=self.device)
-        p = self.plan(mat_ids, uv_image)
+        if not out.is_contiguous() or out.dtype != self.out_dtype or tuple(out.shape) != (h, w, self.n_out):
+            raise ValueError("out must be a contiguous [H][W][C] image of the decoder's dtype")
+        p = self.plan(mat_ids, uv_image, out=out, indexed=indexed)
         if p["plan"] is not None:
             p["plan"].launch()
-            scatter_rows(p["rows"], p["pixel_list"], out)
+            if not indexed:
+                scatter_rows(p["rows"], p["pixel_list"], out)
         return out
 
 

@@ -571,6 +571,15 @@ ntc_status setup_batch(const ntc_material *mats, int32_t n_mats, const ntc_batch
       return fail(NTC_E_ALIGN, "material %d: misaligned pointer", m);
     if (M.out_dtype != NTC_F32 && M.out_dtype != NTC_F16)
       return fail(NTC_E_UNSUPPORTED, "material %d: out dtype %d", m, M.out_dtype);
+    if (M.pixel_index) {
+      const int64_t esz = M.out_dtype == NTC_F16 ? 2 : 4;
+      if (!aligned(M.pixel_index, 4)) return fail(NTC_E_ALIGN, "material %d: pixel_index misaligned", m);
+      if (M.image_pixels < 1 || M.image_pixels * s.n_out * esz >= ((int64_t)1 << 30) ||
+          M.image_pixels * 8 >= ((int64_t)1 << 30))
+        return fail(NTC_E_SHAPE, "material %d: image_pixels %lld outside 1..2^30 bytes of uv and output", m,
+                    (long long)M.image_pixels);
+      if (M.n > ((int64_t)1 << 28)) return fail(NTC_E_SHAPE, "material %d: indexed n above 2^28", m);
+    }
     BatchMaterial &B = b->mats[m];
     memset(&B, 0, sizeof B);
     B.a.lat = to_lat_args(&M.lat);
@@ -584,6 +593,8 @@ ntc_status setup_batch(const ntc_material *mats, int32_t n_mats, const ntc_batch
     B.a.stage_cap = cap;
     B.a.n_layers = s.n_layers;
     B.a.lay = pack_layout(s, NTC_F16);
+    B.a.pix = M.pixel_index;
+    B.a.img_px = M.pixel_index ? M.image_pixels : 0;
     B.shape_id = sid;
     B.hid = s.hid;
     B.n_layers = s.n_layers;

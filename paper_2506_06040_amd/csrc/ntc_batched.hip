@@ -25,7 +25,7 @@ namespace ntc {
 // 64-pixel tiles per span of the batched walk.
 constexpr int kBatchSpanTiles = NTC_SPAN_TILES;
 
-template <int HID, int NL, bool VEC4>
+template <int HID, int NL, bool VEC4, bool IDX>
 __device__ __forceinline__ void run_material(const BatchMaterial &M, const BatchItem *items, int it0, int it1,
                                              f32x4 *stage, f32x4 *bias, f32x4 *ltab) {
   constexpr int ST = kBatchSpanTiles;
@@ -48,7 +48,7 @@ __device__ __forceinline__ void run_material(const BatchMaterial &M, const Batch
   SpanUv<ST> uvs;
   int it = it0;
   int64_t tile = items[it0].first_tile;
-  uvs.load(a.uv, tile * 64, item_end(it0));
+  uvs.template load_any<IDX>(a, tile * 64, item_end(it0));
   uvs.ready();
   while (it < it1) {
     const int64_t end_px = item_end(it);
@@ -58,7 +58,7 @@ __device__ __forceinline__ void run_material(const BatchMaterial &M, const Batch
       ++nit;
       ntile = nit < it1 ? items[nit].first_tile : -1;
     }
-    decode_span<PrecF16, HID, NL, ST, VEC4>(a, tile * 64, end_px, stage, bias, ltab, W, uvs,
+    decode_span<PrecF16, HID, NL, ST, VEC4, IDX>(a, tile * 64, end_px, stage, bias, ltab, W, uvs,
                                             nit < it1 ? ntile * 64 : -1, nit < it1 ? item_end(nit) : 0);
     it = nit;
     tile = ntile;
@@ -83,9 +83,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
     while (run_end < end && items[run_end].mat == m) ++run_end;
     const BatchMaterial &M = mats[m];
     const bool vec4 = (M.a.n_out & 3) == 0;
-#define NTC_RUN(HID, NL)                                                     \
-  (vec4 ? run_material<HID, NL, true>(M, items, it, run_end, stage, bias, ltab) \
-        : run_material<HID, NL, false>(M, items, it, run_end, stage, bias, ltab))
+#define NTC_RUN(HID, NL)                                                                    \
+  (M.a.pix ? (vec4 ? run_material<HID, NL, true, true>(M, items, it, run_end, stage, bias, ltab)     \
+                   : run_material<HID, NL, false, true>(M, items, it, run_end, stage, bias, ltab))   \
+           : (vec4 ? run_material<HID, NL, true, false>(M, items, it, run_end, stage, bias, ltab)    \
+                   : run_material<HID, NL, false, false>(M, items, it, run_end, stage, bias, ltab)))
     switch (M.shape_id) {
       case 0: NTC_RUN(16, 2); break;
       case 1: NTC_RUN(16, 3); break;

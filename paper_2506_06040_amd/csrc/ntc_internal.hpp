@@ -69,6 +69,8 @@ struct DecodeArgs {
   int32_t stage_cap;    // texels per wave in LDS
   int32_t n_layers;
   PackLayout lay;
+  const int32_t *pix;   // optional: sample s is pixel pix[s] of the uv / out images
+  int64_t img_px;       // pixels of those images
 };
 
 hipError_t launch_decode_plain(const DecodeArgs &a, const MlpShape &s, float *calib_amax, int n_cus,

@@ -549,9 +549,9 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
 
 // Sigmoid of the output pre-activations of NT N-tiles (N-tiles t0 .. t0 +
 // NT - 1 of the span) and store. VEC4: the output width is a multiple of 4.
-template <class P, int NT, bool VEC4>
+template <class P, int NT, bool VEC4, bool IDX = false>
 __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buffer_rsrc_t ors,
-                                              const f32x16 (&z)[NT], int t0) {
+                                              const f32x16 (&z)[NT], int t0, int64_t first = 0, int span = 0) {
   const int lane = (threadIdx.x & 63);
   const int h = lane >> 5;
   const int n = lane & 31;
@@ -565,7 +565,13 @@ __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buff
   const bool two_groups = n_out > 8;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const int pix = 32 * (t0 + t) + n;
+    int pix = 32 * (t0 + t) + n;
+    if constexpr (IDX) {
+      // the output row of an indexed sample is its pixel in the image (ors
+      // covers the whole image); samples past the span are dropped
+      const int64_t r = pix < span ? (int64_t)a.pix[first + pix] : -1;
+      pix = (int)((r >= 0 && r < a.img_px) ? r : a.img_px);  // one past the image: dropped
+    }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       if (j == 0 || two_groups) {
@@ -610,13 +616,14 @@ __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buff
 
 // MLP over NT N-tiles of 32 pixels (N-tiles t0 .. t0 + NT - 1 of the span) and
 // store.
-template <class P, int HID, int NL, int NT, bool VEC4, bool UNIT>
+template <class P, int HID, int NL, int NT, bool VEC4, bool UNIT, bool IDX = false>
 __device__ __forceinline__ void mlp_store(const DecodeArgs &a, const MfmaWeights<P, HID, NL> &W,
                                           const f32x4 *bias, __amdgpu_buffer_rsrc_t ors,
-                                          const typename P::Frag (&bx)[NT], int t0, int salt) {
+                                          const typename P::Frag (&bx)[NT], int t0, int salt, int64_t first = 0,
+                                          int span = 0) {
   f32x16 z[NT];
   mlp_compute<P, HID, NL, NT, UNIT>(W, bias, bx, z, salt);
-  store_outputs<P, NT, VEC4>(a, ors, z, t0);
+  store_outputs<P, NT, VEC4, IDX>(a, ors, z, t0, first, span);
 }
 
 
@@ -711,6 +718,32 @@ struct SpanUv {
       u[q] = __uint_as_float(w[0]);
       v[q] = __uint_as_float(w[1]);
     }
+  }
+  // Indexed samples: sample s is pixel pix[s] of a uv image of img_px pixels
+  // (img_px * 8 < 2^32). An index outside the image reads (0, 0).
+  __device__ __forceinline__ void load_idx(const float2 *uv_img, int64_t img_px, const int32_t *pix,
+                                           int64_t first_px, int64_t end_px) {
+    const int lane = (threadIdx.x & 63);
+    const int64_t left = end_px - first_px;
+    const int span = left < 64 * ST ? (int)left : 64 * ST;
+    const __amdgpu_buffer_rsrc_t irs = make_rsrc(pix + first_px, (uint32_t)span * 4u);
+    const __amdgpu_buffer_rsrc_t urs = make_rsrc(uv_img, (uint32_t)(img_px * 8));
+#pragma unroll
+    for (int q = 0; q < ST; ++q) {
+      const int p = min(64 * q + lane, span - 1);
+      const int idx = (int)__builtin_amdgcn_raw_buffer_load_b32(irs, p * 4, 0, 0);
+      const uint32_t off = (idx >= 0 && (int64_t)idx < img_px) ? (uint32_t)idx * 8u : 0xFFFFFFF0u;
+      const auto w = __builtin_amdgcn_raw_buffer_load_b64(urs, off, 0, 0);
+      u[q] = __uint_as_float(w[0]);
+      v[q] = __uint_as_float(w[1]);
+    }
+  }
+  template <bool IDX>
+  __device__ __forceinline__ void load_any(const DecodeArgs &a, int64_t first_px, int64_t end_px) {
+    if constexpr (IDX)
+      load_idx(a.uv, a.img_px, a.pix, first_px, end_px);
+    else
+      load(a.uv, first_px, end_px);
   }
   // wait for the loads here (an empty asm that reads every coordinate)
   __device__ __forceinline__ void ready() const {
@@ -950,10 +983,10 @@ __device__ __forceinline__ void direct_operands(const DecodeArgs &a, const f32x4
 
 // MLP and store of sub-span q of a span (two N-tiles of 32 pixels). UNIT:
 // ReLU by the [0, 1] clamp (see PrecF16::next_operands).
-template <class P, int HID, int NL, bool VEC4, bool UNIT>
+template <class P, int HID, int NL, bool VEC4, bool UNIT, bool IDX = false>
 __device__ __forceinline__ void subspan_mlp(const DecodeArgs &a, const MfmaWeights<P, HID, NL> &W, const f32x4 *bias,
                                             __amdgpu_buffer_rsrc_t ors, const typename P::Frag (&bx)[2], int q,
-                                            int salt) {
+                                            int salt, int64_t first = 0, int span = 0) {
   using Frag = typename P::Frag;
   // The other wave of the SIMD is usually sampling (vector work): issuing
   // this wave's matrix chain first lets the two overlap instead of both
@@ -963,10 +996,10 @@ __device__ __forceinline__ void subspan_mlp(const DecodeArgs &a, const MfmaWeigh
   // accumulators, otherwise one after the other
   if constexpr (HID >= 64 && NL >= 3 && NTC_WIDE_NT == 1) {
     const Frag b0[1] = {bx[0]}, b1[1] = {bx[1]};
-    mlp_store<P, HID, NL, 1, VEC4, UNIT>(a, W, bias, ors, b0, 2 * q, salt);
-    mlp_store<P, HID, NL, 1, VEC4, UNIT>(a, W, bias, ors, b1, 2 * q + 1, salt + 1);
+    mlp_store<P, HID, NL, 1, VEC4, UNIT, IDX>(a, W, bias, ors, b0, 2 * q, salt, first, span);
+    mlp_store<P, HID, NL, 1, VEC4, UNIT, IDX>(a, W, bias, ors, b1, 2 * q + 1, salt + 1, first, span);
   } else {
-    mlp_store<P, HID, NL, 2, VEC4, UNIT>(a, W, bias, ors, bx, 2 * q, salt);
+    mlp_store<P, HID, NL, 2, VEC4, UNIT, IDX>(a, W, bias, ors, bx, 2 * q, salt, first, span);
   }
   __builtin_amdgcn_s_setprio(0);
 }
@@ -981,7 +1014,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t span_out(const DecodeArgs &a, 
 // already in uvs) and ending before end_px: footprint, staging, sampling,
 // MLP, store. The uv of the next span (next_first < 0: none) is requested
 // during this span, so that its latency overlaps the work of the span.
-template <class P, int HID, int NL, int ST, bool VEC4>
+template <class P, int HID, int NL, int ST, bool VEC4, bool IDX = false>
 __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, int64_t end_px, f32x4 *stage,
                                             const f32x4 *bias, f32x4 *ltab, const MfmaWeights<P, HID, NL> &W,
                                             SpanUv<ST> &uvs, int64_t next_first, int64_t next_end_px) {
@@ -989,9 +1022,11 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
   const int64_t left = end_px - first;
   const int span = left < 64 * ST ? (int)left : 64 * ST;
   const int span_salt = (int)first;
-  const __amdgpu_buffer_rsrc_t ors = span_out(a, first, span);
+  // indexed samples write into the whole output image
+  const __amdgpu_buffer_rsrc_t ors =
+      IDX ? make_rsrc(a.out, (uint32_t)(a.img_px * a.n_out * (a.out_f16 ? 2 : 4))) : span_out(a, first, span);
 
-  if (!NTC_UV_PREFETCH) uvs.load(a.uv, first, end_px);
+  if (!NTC_UV_PREFETCH) uvs.template load_any<IDX>(a, first, end_px);
   float u[ST], v[ST];
 #pragma unroll
   for (int q = 0; q < ST; ++q) {
@@ -1014,12 +1049,12 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     // ST sub-spans below (all of them run, also past the end of a short span,
     // whose stores the range check drops): that fixed count lets the wait
     // for these uv at the next span leave the stores in flight.
-    if (NTC_UV_PREFETCH && next_first >= 0) uvs.load(a.uv, next_first, next_end_px);
+    if (NTC_UV_PREFETCH && next_first >= 0) uvs.template load_any<IDX>(a, next_first, next_end_px);
     NTC_UNROLL_STAGED
     for (int q = 0; q < ST; ++q) {
       Frag bx[2];
       staged_operands<P>(a, stage, ltab, kbw, kbase, u[q], v[q], W.in_scale, span_salt + q, bx);
-      subspan_mlp<P, HID, NL, VEC4, P::kUnitReLU>(a, W, bias, ors, bx, q, span_salt + 2 * q);
+      subspan_mlp<P, HID, NL, VEC4, P::kUnitReLU, IDX>(a, W, bias, ors, bx, q, span_salt + 2 * q, first, span);
     }
     return;
   }
@@ -1036,12 +1071,12 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     }
     Frag bx[2];
     direct_operands<P>(a, ltab, uq, vq, W.in_scale, q, bx);
-    subspan_mlp<P, HID, NL, VEC4, false>(a, W, bias, ors, bx, q, 2 * q);
+    subspan_mlp<P, HID, NL, VEC4, false, IDX>(a, W, bias, ors, bx, q, 2 * q, first, span);
   }
   // the next span's uv, completed here: this path then leaves no pending
   // load behind and the wait state where the paths join is the staged one
   if (NTC_UV_PREFETCH && next_first >= 0) {
-    uvs.load(a.uv, next_first, next_end_px);
+    uvs.template load_any<IDX>(a, next_first, next_end_px);
     uvs.ready();
   }
 }

@@ -79,7 +79,10 @@ def test_frame_decode_equals_per_material_and_oracle():
     fd = ntc.FrameDecoder(mats)
     mat_t = torch.from_numpy(mat).cuda()
     uv_t = torch.from_numpy(np.ascontiguousarray(uv_img)).cuda()
-    out = fd.decode(mat_t, uv_t).cpu().numpy().reshape(-1, 8)
+    out_t = fd.decode(mat_t, uv_t)
+    # the decode through the pixel lists equals gather + decode + scatter
+    assert torch.equal(out_t, fd.decode(mat_t, uv_t, indexed=False))
+    out = out_t.cpu().numpy().reshape(-1, 8)
     lst, off, _, _ = ntc.classify(mat_t, n_mats)
     lst, off = lst.cpu().numpy(), off.cpu().numpy()
     flat_uv = uv_img.reshape(-1, 2)
@@ -95,3 +98,28 @@ def test_frame_decode_equals_per_material_and_oracle():
         err = np.abs(out[pix] - ref).max()
         print(f"[frame decode] material {m}: {pix.size} px, max err {err:.2e}", flush=True)
         assert err <= 2e-3, m
+
+
+def test_batched_indexed_ignores_invalid_indices():
+    """Indices outside the image read uv (0, 0) and write nothing; valid ones
+    equal the plain decode of the same uv."""
+    ntc = _ntc()
+    rng = np.random.default_rng(10)
+    h, w = 64, 96
+    lat_np = I.bc1_pyramid(rng, [(64, 64), (32, 32), (16, 16), (8, 8)])
+    Ws, bs = I.xavier_mlp(rng, (14, 32, 32, 8), bias="normal")
+    lat, mlp = ntc.Latents(lat_np, shift=I.PAPER_SHIFT), ntc.Mlp(Ws, bs)
+    uv_img = torch.from_numpy(rng.random((h * w, 2)).astype(np.float32)).cuda()
+    idx = rng.permutation(h * w)[:2000].astype(np.int32)
+    idx[::97] = -1
+    idx[5::97] = h * w + 3
+    out = torch.full((h * w, 8), 7.0, device="cuda")
+    m = ntc.Material(lat, mlp, uv_img, out=out, pixel_index=torch.from_numpy(idx).cuda())
+    ntc.BatchPlan([m]).launch()
+    torch.cuda.synchronize()
+    good = idx[(idx >= 0) & (idx < h * w)]
+    ref = ntc.decode(lat, mlp, uv_img[torch.from_numpy(good).long().cuda()].contiguous(), compute="f16")
+    got = out.cpu().numpy()
+    assert np.array_equal(got[good], ref.cpu().numpy())
+    untouched = np.setdiff1d(np.arange(h * w), good)
+    assert np.all(got[untouched] == 7.0)
