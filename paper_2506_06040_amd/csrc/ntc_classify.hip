@@ -59,6 +59,10 @@ __device__ __forceinline__ StepPixel step_pixel(const ClassifyArgs &a, int chunk
   return p;
 }
 
+// Steps are taken kPrefetch at a time: their material ids are loaded first,
+// so that one wait covers all of them instead of one load latency per step.
+constexpr int kPrefetch = 8;
+
 // Kind of the pixel's tile (0 simple, 1 other) and the tile's class
 // (0 no neural pixel, 1 simple, 2 mixed or sparse), from the 32 lanes of
 // its half of the wavefront.
@@ -88,20 +92,26 @@ __global__ __launch_bounds__(64) void classify_count_kernel(ClassifyArgs a) {
   const int n_keys = 2 * a.n_mats;
   for (int k = lane; k < n_keys; k += 64) cnt[k] = 0;
   __syncthreads();
-  for (int s = 0; s < kTilesPerChunk / 2; ++s) {
-    const StepPixel p = step_pixel(a, chunk, s, lane);
-    const bool valid = p.m < (uint32_t)a.n_mats;
-    int kind, cls;
-    tile_kind(valid, p.m, lane, kind, cls);
-    if (a.tile_class && (lane & 31) == 0 && p.tile < a.n_tiles) a.tile_class[p.tile] = (uint8_t)cls;
-    const int key = valid ? 2 * (int)p.m + kind : -1;
-    uint64_t pending = __ballot(valid);
-    while (pending) {
-      const int leader = __builtin_ctzll(pending);
-      const int k = __builtin_amdgcn_readlane(key, leader);
-      const uint64_t same = __ballot(key == k);
-      if (lane == 0) cnt[k] += __popcll(same);
-      pending &= ~same;
+  for (int s0 = 0; s0 < kTilesPerChunk / 2; s0 += kPrefetch) {
+    StepPixel ps[kPrefetch];
+#pragma unroll
+    for (int i = 0; i < kPrefetch; ++i) ps[i] = step_pixel(a, chunk, s0 + i, lane);
+#pragma unroll
+    for (int i = 0; i < kPrefetch; ++i) {
+      const StepPixel p = ps[i];
+      const bool valid = p.m < (uint32_t)a.n_mats;
+      int kind, cls;
+      tile_kind(valid, p.m, lane, kind, cls);
+      if (a.tile_class && (lane & 31) == 0 && p.tile < a.n_tiles) a.tile_class[p.tile] = (uint8_t)cls;
+      const int key = valid ? 2 * (int)p.m + kind : -1;
+      uint64_t pending = __ballot(valid);
+      while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const int k = __builtin_amdgcn_readlane(key, leader);
+        const uint64_t same = __ballot(key == k);
+        if (lane == 0) cnt[k] += __popcll(same);
+        pending &= ~same;
+      }
     }
   }
   __syncthreads();
@@ -172,23 +182,29 @@ __global__ __launch_bounds__(64) void classify_write_kernel(ClassifyArgs a) {
     run[k] = a.mat_offsets[m] + ((k & 1) ? a.totals[k - 1] : 0) + a.counts[(int64_t)k * a.n_chunks + chunk];
   }
   __syncthreads();
-  for (int s = 0; s < kTilesPerChunk / 2; ++s) {
-    const StepPixel p = step_pixel(a, chunk, s, lane);
-    const bool valid = p.m < (uint32_t)a.n_mats;
-    int kind, cls;
-    tile_kind(valid, p.m, lane, kind, cls);
-    const int key = valid ? 2 * (int)p.m + kind : -1;
-    uint64_t pending = __ballot(valid);
-    while (pending) {
-      const int leader = __builtin_ctzll(pending);
-      const int k = __builtin_amdgcn_readlane(key, leader);
-      const uint64_t same = __ballot(key == k);
-      const int base = run[k];
-      if (key == k) a.list[base + (int)lanes_below(same)] = p.idx;
-      // every lane has read run[k] before lane 0 moves it (one wavefront,
-      // LDS operations complete in order)
-      if (lane == 0) run[k] = base + __popcll(same);
-      pending &= ~same;
+  for (int s0 = 0; s0 < kTilesPerChunk / 2; s0 += kPrefetch) {
+    StepPixel ps[kPrefetch];
+#pragma unroll
+    for (int i = 0; i < kPrefetch; ++i) ps[i] = step_pixel(a, chunk, s0 + i, lane);
+#pragma unroll
+    for (int i = 0; i < kPrefetch; ++i) {
+      const StepPixel p = ps[i];
+      const bool valid = p.m < (uint32_t)a.n_mats;
+      int kind, cls;
+      tile_kind(valid, p.m, lane, kind, cls);
+      const int key = valid ? 2 * (int)p.m + kind : -1;
+      uint64_t pending = __ballot(valid);
+      while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const int k = __builtin_amdgcn_readlane(key, leader);
+        const uint64_t same = __ballot(key == k);
+        const int base = run[k];
+        if (key == k) a.list[base + (int)lanes_below(same)] = p.idx;
+        // every lane has read run[k] before lane 0 moves it (one wavefront,
+        // LDS operations complete in order)
+        if (lane == 0) run[k] = base + __popcll(same);
+        pending &= ~same;
+      }
     }
   }
 }
