@@ -106,9 +106,18 @@ __global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a, const floa
                                                       const float *__restrict__ W3, const float *__restrict__ b0,
                                                       const float *__restrict__ b1, const float *__restrict__ b2,
                                                       const float *__restrict__ b3) {
-  // layer l's parameters (l is a constant wherever this is called)
-  auto Wl = [&](int l) { return l == 0 ? W0 : (l == 1 ? W1 : (l == 2 ? W2 : W3)); };
-  auto bl = [&](int l) { return l == 0 ? b0 : (l == 1 ? b1 : (l == 2 ? b2 : b3)); };
+  // Layer l's parameters (l is a constant wherever this is called), offset
+  // by a zero the compiler cannot see through: `salt` differs per chunk and
+  // per use, so the scalar loads of the weights stay where they are used
+  // instead of being hoisted out of the chunk loop or shared between the
+  // forward and the backward (thousands of weights held in scalar registers
+  // would spill into vector lanes).
+  auto Wl = [&](int l, int salt) {
+    return (l == 0 ? W0 : (l == 1 ? W1 : (l == 2 ? W2 : W3))) + opaque_zero(salt);
+  };
+  auto bl = [&](int l, int salt) {
+    return (l == 0 ? b0 : (l == 1 ? b1 : (l == 2 ? b2 : b3))) + opaque_zero(salt);
+  };
   using Dm = BwdDims<HID, NL>;
   extern __shared__ float smem[];
   // LDS: per-layer padded accumulators (W then b), then the D / A staging.
@@ -137,6 +146,7 @@ __global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a, const floa
   const int n_levels = a.lat.n_levels;
   const int64_t n_chunks = (a.n + 63) / 64;
   for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+    const int salt = (int)chunk * 16;
     const int64_t s = chunk * 64 + lane;
     const bool valid = s < a.n;
     const float2 uv = a.uv[valid ? s : a.n - 1];
@@ -161,8 +171,8 @@ __global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a, const floa
     }
     float h[NL - 1][HID];
     {
-      const float *W = Wl(0);
-      const float *b = bl(0);
+      const float *W = Wl(0, salt);
+      const float *b = bl(0, salt);
       const int in0 = a.dims[0];
 #pragma unroll
       for (int o = 0; o < HID; ++o) {
@@ -175,8 +185,8 @@ __global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a, const floa
     }
 #pragma unroll
     for (int l = 1; l < NL - 1; ++l) {
-      const float *W = Wl(l);
-      const float *b = bl(l);
+      const float *W = Wl(l, salt + l);
+      const float *b = bl(l, salt + l);
 #pragma unroll
       for (int o = 0; o < HID; ++o) {
         float z = b[o];
@@ -187,8 +197,8 @@ __global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a, const floa
     }
     float d[HID > 16 ? HID : 16];
     {
-      const float *W = Wl(NL - 1);
-      const float *b = bl(NL - 1);
+      const float *W = Wl(NL - 1, salt + NL);
+      const float *b = bl(NL - 1, salt + NL);
 #pragma unroll
       for (int o = 0; o < 16; ++o) {
         d[o] = 0.f;
@@ -238,7 +248,7 @@ __global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a, const floa
       (void)K;
       if (l > 0) {
         // D_{l-1} = (W_l^T D_l) * [A_l > 0]
-        const float *W = Wl(l);
+        const float *W = Wl(l, salt + 2 * NL + l);
         const int rows = (l == NL - 1) ? n_out : HID;
         float nd[HID];
 #pragma unroll
@@ -256,7 +266,7 @@ __global__ __launch_bounds__(64) void backward_kernel(BackwardArgs a, const floa
         for (int k = HID; k < (HID > 16 ? HID : 16); ++k) d[k] = 0.f;
       } else if (valid) {
         // dx = W_0^T D_0, spread onto the taps of every level
-        const float *W = Wl(0);
+        const float *W = Wl(0, salt + 3 * NL);
         const int in0 = a.dims[0];
         float dx[12];
 #pragma unroll
@@ -319,11 +329,26 @@ struct ReduceArgs {
 };
 
 // grad[p] = sum over workgroups of part[b][p], added in FP64, rounded once.
-__global__ void reduce_f64_kernel(ReduceArgs r) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= r.n_params) return;
+// A workgroup owns 64 consecutive parameters (one per lane, coalesced
+// loads); its kReduceWaves wavefronts each add every kReduceWaves-th
+// workgroup's partials, and the wavefront sums are then added in wavefront
+// order, so the result does not depend on timing.
+constexpr int kReduceWaves = 16;
+__global__ __launch_bounds__(64 * kReduceWaves) void reduce_f64_kernel(ReduceArgs r) {
+  __shared__ double wsum[kReduceWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int b = 0; b < r.n_blocks; ++b) s += (double)r.part[(int64_t)b * r.n_params + p];
+  if (p < r.n_params) {
+#pragma unroll 8
+    for (int b = w; b < r.n_blocks; b += kReduceWaves) s += (double)r.part[(int64_t)b * r.n_params + p];
+  }
+  wsum[w][lane] = s;
+  __syncthreads();
+  if (w != 0 || p >= r.n_params) return;
+  s = 0.0;
+#pragma unroll
+  for (int i = 0; i < kReduceWaves; ++i) s += wsum[i][lane];
   int off = p;
   for (int l = 0; l < r.n_layers; ++l) {
     const int nw = r.dims[l] * r.dims[l + 1];
@@ -393,8 +418,7 @@ hipError_t launch_backward(const BackwardArgs &a, const MlpShape &s, float *cons
     r.W[l] = grad_W[l];
     r.b[l] = grad_b[l];
   }
-  const int bs = 256;
-  hipLaunchKernelGGL(reduce_f64_kernel, dim3((a.n_params + bs - 1) / bs), dim3(bs), 0, st, r);
+  hipLaunchKernelGGL(reduce_f64_kernel, dim3((a.n_params + 63) / 64), dim3(64 * kReduceWaves), 0, st, r);
   return hipGetLastError();
 }
 

@@ -39,6 +39,19 @@ struct LatArgs {
   int32_t pad_;
 };
 
+// A zero the compiler cannot see through, computed from a loop-variant
+// (wavefront-uniform) `salt`. Offsetting a table pointer by it inside a loop
+// keeps loop-invariant code motion from turning the table (bias fragments,
+// level parameters, weights) into registers held across the loop, and keeps
+// two reads of one value in different places from being merged; the table is
+// read again where it is used instead. The asm is not volatile, so it orders
+// no memory access and the scheduler stays free to interleave the reads.
+__device__ __forceinline__ int opaque_zero(int salt) {
+  int z;
+  asm("s_mov_b32 %0, 0 ; %1" : "=s"(z) : "s"(salt));
+  return z;
+}
+
 // Endpoint fields of an RGB565 word rearranged as red | blue << 8 | green << 16.
 __device__ __forceinline__ uint32_t endpoint_fields(uint32_t c) {
   return (c >> 11) | ((c & 31u) << 8) | (((c >> 5) & 63u) << 16);

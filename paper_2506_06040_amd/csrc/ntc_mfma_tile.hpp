@@ -291,41 +291,12 @@ __device__ __forceinline__ void set_dword(typename P::Frag &f, int d, unsigned w
   }
 }
 
-// A zero the compiler cannot see through, computed from a loop-variant
-// `salt`. Offsetting an LDS table pointer by it inside a loop keeps
-// loop-invariant code motion from turning the table (bias fragments, level
-// parameters) into registers held across the loop; the table is read again
-// where it is used instead. The asm is not volatile, so it orders no memory
-// access and the scheduler stays free to interleave the reads.
-__device__ __forceinline__ int opaque_zero(int salt) {
-  int z;
-  asm("s_mov_b32 %0, 0 ; %1" : "=s"(z) : "s"(salt));
-  return z;
-}
-
-// Minimum / maximum over the 16 lanes of a DPP row (row rotations).
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float row_min(float v) {
-  v = fminf(v, dpp_f<0x128>(v));
-  v = fminf(v, dpp_f<0x124>(v));
-  v = fminf(v, dpp_f<0x122>(v));
-  v = fminf(v, dpp_f<0x121>(v));
-  return v;
-}
-__device__ __forceinline__ float row_max(float v) {
-  v = fmaxf(v, dpp_f<0x128>(v));
-  v = fmaxf(v, dpp_f<0x124>(v));
-  v = fmaxf(v, dpp_f<0x122>(v));
-  v = fmaxf(v, dpp_f<0x121>(v));
-  return v;
-}
-
+// Minimum / maximum over the 16 lanes of a DPP row (row rotations). A
+// rotation reads a valid lane everywhere, so bound_ctrl changes no value; it
+// lets the compiler fold the move into the min / max (v_min_i32_dpp).
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 __device__ __forceinline__ int row_min_i(int v) {
   v = min(v, dpp_i<0x128>(v));
@@ -340,10 +311,6 @@ __device__ __forceinline__ int row_max_i(int v) {
   v = max(v, dpp_i<0x122>(v));
   v = max(v, dpp_i<0x121>(v));
   return v;
-}
-
-__device__ __forceinline__ float uniform_f(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
 }
 
 // Register-resident weights of one MLP (32-row M-tiles, K-steps of the
@@ -759,21 +726,26 @@ struct SpanUv {
 // edge for the level sizes the library accepts).
 __device__ __forceinline__ float tap_coord(float u) { return fminf(fmaxf(u, -1048576.0f), 1048576.0f); }
 
-__device__ __forceinline__ float wave_min(float v) {
-  v = row_min(v);
-  const float a = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
-  const float b = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
-  const float c = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
-  const float d = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
-  return uniform_f(fminf(fminf(a, b), fminf(c, d)));
+// Signed integer with the order of a non-NaN float (negative floats have
+// their magnitude bits flipped); the map is its own inverse. Reductions over
+// these keys are integer DPP minimum / maximum (one instruction per step,
+// with no NaN canonicalisation) finished on the scalar unit.
+__device__ __forceinline__ int order_key(float f) {
+  const int b = __float_as_int(f);
+  return b ^ ((b >> 31) & 0x7fffffff);
 }
-__device__ __forceinline__ float wave_max(float v) {
-  v = row_max(v);
-  const float a = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
-  const float b = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
-  const float c = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
-  const float d = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
-  return uniform_f(fmaxf(fmaxf(a, b), fmaxf(c, d)));
+__device__ __forceinline__ float key_float(int k) { return __int_as_float(k ^ ((k >> 31) & 0x7fffffff)); }
+__device__ __forceinline__ float wave_min_key(float v) {
+  const int r = row_min_i(order_key(v));
+  const int a = __builtin_amdgcn_readlane(r, 0), b = __builtin_amdgcn_readlane(r, 16);
+  const int c = __builtin_amdgcn_readlane(r, 32), d = __builtin_amdgcn_readlane(r, 48);
+  return key_float(min(min(a, b), min(c, d)));
+}
+__device__ __forceinline__ float wave_max_key(float v) {
+  const int r = row_max_i(order_key(v));
+  const int a = __builtin_amdgcn_readlane(r, 0), b = __builtin_amdgcn_readlane(r, 16);
+  const int c = __builtin_amdgcn_readlane(r, 32), d = __builtin_amdgcn_readlane(r, 48);
+  return key_float(max(max(a, b), max(c, d)));
 }
 
 // Operand exchange between the lane halves. Each lane computes all features
@@ -820,10 +792,11 @@ __device__ __forceinline__ bool stage_span(const DecodeArgs &a, const float (&u)
     vmin = fminf(vmin, tap_coord(v[q]));
     vmax = fmaxf(vmax, tap_coord(v[q]));
   }
-  umin = wave_min(umin);
-  umax = wave_max(umax);
-  vmin = wave_min(vmin);
-  vmax = wave_max(vmax);
+  // (tap_coord leaves no NaN)
+  umin = wave_min_key(umin);
+  umax = wave_max_key(umax);
+  vmin = wave_min_key(vmin);
+  vmax = wave_max_key(vmax);
   // the sanitised extremes: NaN became -2^20, infinities +-2^20
   in_unit = umin >= 0.0f && umax <= 1.0f && vmin >= 0.0f && vmax <= 1.0f;
   // lane 4 k + s (k < 4): tap index of an extreme coordinate on level k,
@@ -951,9 +924,13 @@ __device__ __forceinline__ void staged_operands(const DecodeArgs &a, const f32x4
       float fx, fy;
       clamp_tap(tap_coord(uq), Lk.fw, Lk.cx, Lk.wm2, i0, fx);
       clamp_tap(tap_coord(vq), Lk.fh, Lk.cy, Lk.hm2, j0, fy);
-      // taps lie inside the staged region of the level
-      const int r = __mul24(j0, kbw[k]) + i0 + kbase[k];
-      const f32x4 t00 = stage[r], t10 = stage[r + 1], t01 = stage[r + kbw[k]], t11 = stage[r + kbw[k] + 1];
+      // taps lie inside the staged region of the level; the row offset is
+      // one multiply-add and the byte address one shift-add (the empty asm
+      // keeps the compiler from distributing the shift over the sum)
+      int r = __mul24(j0, kbw[k]) + i0;
+      asm("" : "+v"(r));
+      const f32x4 *t = stage + kbase[k] + r;
+      const f32x4 t00 = t[0], t10 = t[1], t01 = t[kbw[k]], t11 = t[kbw[k] + 1];
       c = blend4(make_float3(t00[0], t00[1], t00[2]), make_float3(t10[0], t10[1], t10[2]),
                  make_float3(t01[0], t01[1], t01[2]), make_float3(t11[0], t11[1], t11[2]), fx, fy);
     }

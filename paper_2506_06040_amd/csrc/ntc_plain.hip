@@ -346,7 +346,12 @@ __global__ __launch_bounds__(256) void decode_plain_kernel(DecodeArgs a, const f
 #pragma unroll
   for (int l = 0; l < kMaxLayers; ++l) am[l] = 0.f;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.n; p += stride) {
+  int iter = 0;  // wavefront-uniform iteration count: salt of opaque_zero
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.n; p += stride, iter += 4) {
+    // weights read through a per-iteration opaque offset, so that their
+    // scalar loads stay in the loop instead of being hoisted out of it into
+    // scalar registers that spill into vector lanes
+    const float *wpi = wp + opaque_zero(iter);
     const float2 uv = a.uv[p];
     float x[16];
 #pragma unroll
@@ -371,8 +376,8 @@ __global__ __launch_bounds__(256) void decode_plain_kernel(DecodeArgs a, const f
     }
     float h[HID];
     {
-      const float *W = wp + a.lay.w_off[0] / 4;
-      const float *b = wp + a.lay.b_off[0] / 4;
+      const float *W = wpi + a.lay.w_off[0] / 4;
+      const float *b = wpi + a.lay.b_off[0] / 4;
 #pragma unroll
       for (int o = 0; o < HID; ++o) {
         float acc = b[o];
@@ -386,8 +391,8 @@ __global__ __launch_bounds__(256) void decode_plain_kernel(DecodeArgs a, const f
 #pragma unroll
         for (int k = 0; k < HID; ++k) am[l] = fmaxf(am[l], h[k]);
       }
-      const float *W = wp + a.lay.w_off[l] / 4;
-      const float *b = wp + a.lay.b_off[l] / 4;
+      const float *W = wpi + a.lay.w_off[l] / 4;
+      const float *b = wpi + a.lay.b_off[l] / 4;
       float h2[HID];
 #pragma unroll
       for (int o = 0; o < HID; ++o) {
@@ -404,8 +409,8 @@ __global__ __launch_bounds__(256) void decode_plain_kernel(DecodeArgs a, const f
       for (int k = 0; k < HID; ++k) am[n_layers - 1] = fmaxf(am[n_layers - 1], h[k]);
       continue;  // calibration only needs the layer inputs
     }
-    const float *W = wp + a.lay.w_off[n_layers - 1] / 4;
-    const float *b = wp + a.lay.b_off[n_layers - 1] / 4;
+    const float *W = wpi + opaque_zero(iter + 1) + a.lay.w_off[n_layers - 1] / 4;
+    const float *b = wpi + opaque_zero(iter + 2) + a.lay.b_off[n_layers - 1] / 4;
 #pragma unroll
     for (int o = 0; o < 16; ++o) {
       if (o < n_out) {
