@@ -113,7 +113,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["f16", "f32", "fp8", "bf16", "varA", "filtered", "bwd", "qat", "batched",
+    ap.add_argument("--only", choices=["f16", "f32", "fp8", "bf16", "varA", "out9", "filtered", "bwd", "qat", "batched",
                                        "copy"],
                     default=None,
                     help="run only one leg (for profiling); 'copy' runs a plain 1 GiB device copy that "
@@ -199,6 +199,23 @@ def main():
                               "frac_fp16_mfma": flops / (ms_a * 1e-3) / 1e12 / PEAK_FP16_TFLOPS,
                               "latents": sizes_a}
         del lat_a
+    if args.only in (None, "out9") and not args.no_extras:
+        # nine output channels: the same network with one more output row
+        # (Xavier-normal like the others, zero bias)
+        log("[bench] FP16 decode, 9 output channels")
+        r9 = I.streams(wl.seed + 300)[1]
+        fan = Ws[-1].shape[1]
+        row = (r9.standard_normal((1, fan)) * np.sqrt(2.0 / (fan + 9))).astype(np.float32)
+        mlp9 = ntc.Mlp(list(Ws[:-1]) + [np.concatenate([Ws[-1], row], 0)],
+                       list(bs[:-1]) + [np.concatenate([bs[-1], np.zeros(1, np.float32)])], device=dev)
+        p9 = ntc.pack(mlp9, "f16")
+        out9 = torch.empty((N, 9), dtype=torch.float32, device=dev)
+        ms9 = time_launches(lambda: ntc.decode(lat, mlp9, uvt, compute="f16", packed=p9, out=out9), args.steps,
+                            args.warmup)
+        flops9 = algorithmic_flops_per_px(tuple(wl.dims[:-1]) + (9,)) * N
+        extras["out9_f16"] = {"Gtexel_per_s": N / (ms9 * 1e-3) / 1e9, "ms": ms9,
+                              "frac_fp16_mfma": flops9 / (ms9 * 1e-3) / 1e12 / PEAK_FP16_TFLOPS}
+        del out9, mlp9, p9
     if args.only in (None, "filtered") and not args.no_extras:
         # mip-mapped latents (2048^2 .. 256^2 levels, full BC1 mip chains),
         # a 4096^2 perspective ground plane with its screen derivatives

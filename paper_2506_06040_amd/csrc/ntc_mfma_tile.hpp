@@ -544,9 +544,12 @@ __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buff
       if (j == 0 || two_groups) {
         f32x4 zj = {z[t][4 * j], z[t][4 * j + 1], z[t][4 * j + 2], z[t][4 * j + 3]};
         if (j > 0) asm volatile("" : "+v"(zj));
-        f32x4 f;
+        // (widths that are not a multiple of 4: rows that are outputs for no
+        // lane of the group are skipped; the test is wavefront-uniform)
+        f32x4 f = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) f[i] = sigmoid_fast(zj[i]);
+        for (int i = 0; i < 4; ++i)
+          if (VEC4 || 8 * j + i < n_out) f[i] = sigmoid_fast(zj[i]);
         const int row = 8 * j + 4 * h;
         // rows past the output width and pixels past the end go beyond the
         // buffer and are dropped by its range check
@@ -561,19 +564,34 @@ __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buff
             __builtin_amdgcn_raw_buffer_store_b128(
                 __builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, f), ors, off, 0, NTC_STORE_AUX);
           }
+        } else if (!a.out_f16) {
+          // FP32 rows of any width: a lane's four values in one 16-byte
+          // store (dword-aligned) where all four are outputs, the others one
+          // by one. Whether some lane needs a store depends only on j and the
+          // width, so stores that no lane needs are not issued.
+          const bool full = row + 4 <= n_out;
+          if (8 * j + 4 <= n_out)
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, f),
+                                                   ors, full ? off0 : 0x7fffffff, 0, NTC_STORE_AUX);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const bool need0 = 8 * j + 4 > n_out && 8 * j + i < n_out;
+            const bool need1 = 8 * j + 8 > n_out && 8 * j + 4 + i < n_out;
+            if (need0 || need1) {
+              // element copied to a scalar first: bit-casting a vector
+              // element in place reads element 0 with this compiler
+              const float fi = f[i];
+              const int oi = (!full && row + i < n_out) ? off0 + i * 4 : 0x7fffffff;
+              __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(fi), ors, oi, 0, NTC_STORE_AUX);
+            }
+          }
         } else {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            // element copied to a scalar first: bit-casting a vector element
-            // in place reads element 0 with this compiler
             const float fi = f[i];
             const int oi = (row + i < n_out) ? off0 + i * esz : 0x7fffffff;
-            if (a.out_f16) {
-              const _Float16 hi = (_Float16)fi;
-              __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, hi), ors, oi, 0, NTC_STORE_AUX);
-            } else {
-              __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(fi), ors, oi, 0, NTC_STORE_AUX);
-            }
+            const _Float16 hi = (_Float16)fi;
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, hi), ors, oi, 0, NTC_STORE_AUX);
           }
         }
       }
