@@ -167,3 +167,23 @@ def test_backward_empty_batch_gives_zero():
                                      torch.zeros((0, 8), device="cuda"))
     torch.cuda.synchronize()
     assert all(float(t.abs().max()) == 0.0 for t in gW + gb + gl)
+
+
+def test_backward_weight_gradients_repeatable():
+    """Weight and bias gradients are sums of per-workgroup FP32 partials added
+    in FP64 in a fixed order, so two calls give the same bits (300k samples:
+    all 1024 workgroups hold partials). Latent gradients come from FP32
+    atomics, whose order varies: equal up to that rounding."""
+    rng = np.random.default_rng(35)
+    sizes = [(256, 256), (128, 128), (64, 64), (32, 32)]
+    lat_np = I.f32_pyramid(rng, sizes)
+    Ws, bs = I.xavier_mlp(rng, (14, 64, 64, 8), bias="normal")
+    uv = I.random_uv(rng, 300_000)
+    g = rng.standard_normal((uv.shape[0], 8)) * 1e-3
+    a = _gpu_direct(lat_np, Ws, bs, uv, g, I.PAPER_SHIFT)
+    b = _gpu_direct(lat_np, Ws, bs, uv, g, I.PAPER_SHIFT)
+    for l in range(3):
+        assert np.array_equal(a[0][l], b[0][l]), f"dW{l}"
+        assert np.array_equal(a[1][l], b[1][l]), f"db{l}"
+    for k in range(4):
+        _close(f"repeat dlat{k}", a[2][k], b[2][k], rtol=1e-5)
