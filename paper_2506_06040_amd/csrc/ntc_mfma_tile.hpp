@@ -518,10 +518,15 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
 // NT - 1 of the span) and store. VEC4: the output width is a multiple of 4.
 template <class P, int NT, bool VEC4, bool IDX = false>
 __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buffer_rsrc_t ors,
-                                              const f32x16 (&z)[NT], int t0, int64_t first = 0, int span = 0) {
+                                              const f32x16 (&z)[NT], int t0, int salt, int64_t first = 0,
+                                              int span = 0) {
   const int lane = (threadIdx.x & 63);
   const int h = lane >> 5;
-  const int n = lane & 31;
+  // Widths that are not a multiple of 4 store up to eight values per lane
+  // and group one by one; their offsets depend only on the lane and the
+  // width, and hoisted out of the persistent loop they would be held (and
+  // spilled) across it. An opaque zero keeps them next to the stores.
+  const int n = (lane & 31) + (VEC4 ? 0 : opaque_zero(salt));
   const int n_out = a.n_out;
   const int esz = a.out_f16 ? 2 : 4;
   // Row groups j (rows 8 j + 4 h .. + 3) that hold outputs for some lane:
@@ -608,7 +613,7 @@ __device__ __forceinline__ void mlp_store(const DecodeArgs &a, const MfmaWeights
                                           int span = 0) {
   f32x16 z[NT];
   mlp_compute<P, HID, NL, NT, UNIT>(W, bias, bx, z, salt);
-  store_outputs<P, NT, VEC4, IDX>(a, ors, z, t0, first, span);
+  store_outputs<P, NT, VEC4, IDX>(a, ors, z, t0, salt, first, span);
 }
 
 
