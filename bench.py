@@ -122,7 +122,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the decode has no cross-GPU step in this build "
+        print("bench.py measures one GPU only: the decode has no cross-GPU step "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 

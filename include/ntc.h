@@ -50,7 +50,7 @@ typedef enum {
     NTC_OK = 0,
     NTC_E_NULL = 1,        /* a required pointer is NULL */
     NTC_E_SHAPE = 2,       /* inconsistent or out-of-range sizes */
-    NTC_E_UNSUPPORTED = 3, /* valid request that this build does not implement */
+    NTC_E_UNSUPPORTED = 3, /* valid request that the library does not implement */
     NTC_E_WORKSPACE = 4,   /* workspace / packed buffer too small */
     NTC_E_HIP = 5,         /* a HIP launch or runtime call failed */
     NTC_E_ALIGN = 6        /* a device pointer is not suitably aligned */

@@ -115,7 +115,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise NtcError(E_HIP, f"libntc.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+            raise NtcError(E_HIP, f"libntc.so is not built ({LIB_PATH}); build it with python paper_2506_06040_amd/build.py")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

@@ -244,7 +244,7 @@ ntc_status ntc_decode(const ntc_latents *lat, const ntc_mlp *mlp, int32_t comput
     if (cfg->stage_capacity) stage_cap = cfg->stage_capacity;
     if (cfg->tiles_per_iter) tiles_per_iter = cfg->tiles_per_iter;
     if (tiles_per_iter != decode_span_tiles())
-      return fail(NTC_E_UNSUPPORTED, "tiles_per_iter %d (this build: %d)", tiles_per_iter, decode_span_tiles());
+      return fail(NTC_E_UNSUPPORTED, "tiles_per_iter %d (compiled for %d)", tiles_per_iter, decode_span_tiles());
   }
   if (waves_per_cu < 1 || waves_per_cu > 1024)
     return fail(NTC_E_SHAPE, "waves_per_cu %d outside 1..1024", waves_per_cu);

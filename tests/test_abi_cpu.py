@@ -21,7 +21,7 @@ def _declared_functions():
 def A():
     from paper_2506_06040_amd import _abi
     if not os.path.exists(_abi.LIB_PATH):
-        pytest.fail("libntc.so is not built; run __graft_entry__.build()")
+        pytest.fail("libntc.so is not built; build it with python paper_2506_06040_amd/build.py")
     _abi.lib()
     return _abi
 
