@@ -27,6 +27,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
   f32x4 *stage = smem;
   f32x4 *bias = smem + a.stage_cap;
   f32x4 *ltab = bias + BiasLds<HID, NL>::kCount;
+  // output staging for widths that are not a multiple of 4 (32 x 16 floats)
+  float *obuf = VEC4 ? nullptr : reinterpret_cast<float *>(ltab + LevelTab::kCount);
   const int lane = threadIdx.x;
 
   MfmaWeights<P, HID, NL> W;
@@ -52,13 +54,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
   for (int64_t it = vb; it < n_spans; it += nb) {
     const int64_t nx = it + nb;
     decode_span<P, HID, NL, ST, VEC4>(a, it * SPX, a.n, stage, bias, ltab, W, uvs, nx < n_spans ? nx * SPX : -1,
-                                      a.n);
+                                      a.n, obuf);
   }
 }
 
 template <class P, int HID, bool VEC4>
 static hipError_t launch_mfma_v(const DecodeArgs &a, int n_layers, int grid, hipStream_t st) {
-  const size_t lds = (size_t)(a.stage_cap + BiasLds<HID, 5>::kCount + LevelTab::kCount) * sizeof(f32x4);
+  const size_t lds =
+      (size_t)(a.stage_cap + BiasLds<HID, 5>::kCount + LevelTab::kCount + (VEC4 ? 0 : 32 * 16 / 4)) * sizeof(f32x4);
   switch (n_layers) {
     case 2: hipLaunchKernelGGL((decode_mfma_kernel<P, HID, 2, VEC4>), dim3(grid), dim3(64), lds, st, a); break;
     case 3: hipLaunchKernelGGL((decode_mfma_kernel<P, HID, 3, VEC4>), dim3(grid), dim3(64), lds, st, a); break;

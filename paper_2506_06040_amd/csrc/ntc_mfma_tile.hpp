@@ -519,7 +519,7 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
 template <class P, int NT, bool VEC4, bool IDX = false>
 __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buffer_rsrc_t ors,
                                               const f32x16 (&z)[NT], int t0, int salt, int64_t first = 0,
-                                              int span = 0) {
+                                              int span = 0, float *obuf = nullptr) {
   const int lane = (threadIdx.x & 63);
   const int h = lane >> 5;
   // Widths that are not a multiple of 4 store up to eight values per lane
@@ -537,6 +537,10 @@ __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buff
   const bool two_groups = n_out > 8;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
+    // FP32 rows whose width is not a multiple of 4, tile of 32 pixels
+    // complete: the rows go through obuf (32 x n_out floats, the tile's
+    // output bytes in order) and leave as contiguous 16-byte stores
+    const bool stg = !VEC4 && !IDX && obuf != nullptr && !a.out_f16 && span >= 32 * (t0 + t + 1);
     int pix = 32 * (t0 + t) + n;
     if constexpr (IDX) {
       // the output row of an indexed sample is its pixel in the image (ors
@@ -559,7 +563,11 @@ __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buff
         // rows past the output width and pixels past the end go beyond the
         // buffer and are dropped by its range check
         const int off0 = (pix * n_out + row) * esz;
-        if (VEC4) {
+        if (stg) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (row + i < n_out) obuf[(lane & 31) * n_out + row + i] = f[i];
+        } else if (VEC4) {
           const int off = row < n_out ? off0 : 0x7fffffff;
           if (a.out_f16) {
             const half4_t hv = __builtin_convertvector(f, half4_t);
@@ -601,6 +609,21 @@ __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buff
         }
       }
     }
+    if (stg) {
+      // The wavefront's LDS accesses complete in order, so the reads see the
+      // rows other lanes just wrote; the empty asm keeps the compiler from
+      // moving LDS accesses across the exchange. 8 n_out chunks of 16 bytes
+      // per tile.
+      asm volatile("" ::: "memory");
+      const int base = 128 * (t0 + t) * n_out;
+      for (int c = lane; c < 8 * n_out; c += 64) {
+        const float *src = obuf + 4 * c;
+        const f32x4 v = {src[0], src[1], src[2], src[3]};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), ors,
+                                               base + 16 * c, 0, NTC_STORE_AUX);
+      }
+      asm volatile("" ::: "memory");
+    }
   }
 }
 
@@ -610,10 +633,10 @@ template <class P, int HID, int NL, int NT, bool VEC4, bool UNIT, bool IDX = fal
 __device__ __forceinline__ void mlp_store(const DecodeArgs &a, const MfmaWeights<P, HID, NL> &W,
                                           const f32x4 *bias, __amdgpu_buffer_rsrc_t ors,
                                           const typename P::Frag (&bx)[NT], int t0, int salt, int64_t first = 0,
-                                          int span = 0) {
+                                          int span = 0, float *obuf = nullptr) {
   f32x16 z[NT];
   mlp_compute<P, HID, NL, NT, UNIT>(W, bias, bx, z, salt);
-  store_outputs<P, NT, VEC4, IDX>(a, ors, z, t0, salt, first, span);
+  store_outputs<P, NT, VEC4, IDX>(a, ors, z, t0, salt, first, span, obuf);
 }
 
 
@@ -986,7 +1009,7 @@ __device__ __forceinline__ void direct_operands(const DecodeArgs &a, const f32x4
 template <class P, int HID, int NL, bool VEC4, bool UNIT, bool IDX = false>
 __device__ __forceinline__ void subspan_mlp(const DecodeArgs &a, const MfmaWeights<P, HID, NL> &W, const f32x4 *bias,
                                             __amdgpu_buffer_rsrc_t ors, const typename P::Frag (&bx)[2], int q,
-                                            int salt, int64_t first = 0, int span = 0) {
+                                            int salt, int64_t first = 0, int span = 0, float *obuf = nullptr) {
   using Frag = typename P::Frag;
   // The other wave of the SIMD is usually sampling (vector work): issuing
   // this wave's matrix chain first lets the two overlap instead of both
@@ -996,10 +1019,10 @@ __device__ __forceinline__ void subspan_mlp(const DecodeArgs &a, const MfmaWeigh
   // accumulators, otherwise one after the other
   if constexpr (HID >= 64 && NL >= 3 && NTC_WIDE_NT == 1) {
     const Frag b0[1] = {bx[0]}, b1[1] = {bx[1]};
-    mlp_store<P, HID, NL, 1, VEC4, UNIT, IDX>(a, W, bias, ors, b0, 2 * q, salt, first, span);
-    mlp_store<P, HID, NL, 1, VEC4, UNIT, IDX>(a, W, bias, ors, b1, 2 * q + 1, salt + 1, first, span);
+    mlp_store<P, HID, NL, 1, VEC4, UNIT, IDX>(a, W, bias, ors, b0, 2 * q, salt, first, span, obuf);
+    mlp_store<P, HID, NL, 1, VEC4, UNIT, IDX>(a, W, bias, ors, b1, 2 * q + 1, salt + 1, first, span, obuf);
   } else {
-    mlp_store<P, HID, NL, 2, VEC4, UNIT, IDX>(a, W, bias, ors, bx, 2 * q, salt, first, span);
+    mlp_store<P, HID, NL, 2, VEC4, UNIT, IDX>(a, W, bias, ors, bx, 2 * q, salt, first, span, obuf);
   }
   __builtin_amdgcn_s_setprio(0);
 }
@@ -1014,10 +1037,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t span_out(const DecodeArgs &a, 
 // already in uvs) and ending before end_px: footprint, staging, sampling,
 // MLP, store. The uv of the next span (next_first < 0: none) is requested
 // during this span, so that its latency overlaps the work of the span.
+// obuf (2 KB of LDS, or nullptr): output staging of the FP32 rows of widths
+// that are not a multiple of 4 (see store_outputs).
 template <class P, int HID, int NL, int ST, bool VEC4, bool IDX = false>
 __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, int64_t end_px, f32x4 *stage,
                                             const f32x4 *bias, f32x4 *ltab, const MfmaWeights<P, HID, NL> &W,
-                                            SpanUv<ST> &uvs, int64_t next_first, int64_t next_end_px) {
+                                            SpanUv<ST> &uvs, int64_t next_first, int64_t next_end_px,
+                                            float *obuf = nullptr) {
   using Frag = typename P::Frag;
   const int64_t left = end_px - first;
   const int span = left < 64 * ST ? (int)left : 64 * ST;
@@ -1054,7 +1080,7 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     for (int q = 0; q < ST; ++q) {
       Frag bx[2];
       staged_operands<P>(a, stage, ltab, kbw, kbase, u[q], v[q], W.in_scale, span_salt + q, bx);
-      subspan_mlp<P, HID, NL, VEC4, P::kUnitReLU, IDX>(a, W, bias, ors, bx, q, span_salt + 2 * q, first, span);
+      subspan_mlp<P, HID, NL, VEC4, P::kUnitReLU, IDX>(a, W, bias, ors, bx, q, span_salt + 2 * q, first, span, obuf);
     }
     return;
   }
@@ -1071,7 +1097,7 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     }
     Frag bx[2];
     direct_operands<P>(a, ltab, uq, vq, W.in_scale, q, bx);
-    subspan_mlp<P, HID, NL, VEC4, false, IDX>(a, W, bias, ors, bx, q, 2 * q, first, span);
+    subspan_mlp<P, HID, NL, VEC4, false, IDX>(a, W, bias, ors, bx, q, 2 * q, first, span, obuf);
   }
   // the next span's uv, completed here: this path then leaves no pending
   // load behind and the wait state where the paths join is the staged one
