@@ -334,3 +334,33 @@ def test_c4_fp8_full_size_sampled(c2_case):
                          c["idx"])
     d = np.abs(got - emu)
     print(f"[c4 fp8 vs emulation] max {d.max():.3g} rms {np.sqrt((d**2).mean()):.3g}", flush=True)
+
+
+def test_extra_output_row_keeps_other_channels_bit_identical():
+    """Output rows are computed independently: a 9-output network whose first
+    8 rows are those of an 8-output network reproduces those 8 channels bit
+    for bit. The 9-channel rows leave through LDS-staged contiguous stores
+    (complete 32-pixel tiles) and single stores (the ragged last tile), the
+    8-channel rows through 16-byte stores per lane; staged and direct
+    sampling. The ninth channel is checked against the oracle."""
+    ntc = _ntc()
+    rng = np.random.default_rng(53)
+    sizes = [(256, 256), (128, 128), (64, 64), (32, 32)]
+    lat_np = I.bc1_pyramid(rng, sizes)
+    Ws, bs = I.xavier_mlp(rng, (14, 64, 64, 64, 8), bias="normal")
+    row = (rng.standard_normal((1, 64)) * 0.15).astype(np.float32)
+    W9 = list(Ws[:-1]) + [np.concatenate([Ws[-1], row], 0)]
+    b9 = list(bs[:-1]) + [np.concatenate([bs[-1], np.float32([0.25])])]
+    uv = I.pixel_uv(512, 128, order="tiled")[:512 * 128 - 37]
+    lat, mlp8 = _gpu_case(lat_np, Ws, bs, I.PAPER_SHIFT)
+    _, mlp9 = _gpu_case(lat_np, W9, b9, I.PAPER_SHIFT)
+    uvt = torch.from_numpy(uv).cuda()
+    olat, omlp9 = _oracle_case(lat_np, W9, b9, I.PAPER_SHIFT)
+    ref9 = O.decode(olat, omlp9, uv)[:, 8:9]
+    for compute, tol in (("f16", TOL_F16_ABS), ("bf16", TOL_BF16_ABS)):
+        for cfg in (None, ntc.tile_cfg(stage_capacity=64)):
+            o8 = ntc.decode(lat, mlp8, uvt, compute=compute, cfg=cfg)
+            o9 = ntc.decode(lat, mlp9, uvt, compute=compute, cfg=cfg)
+            assert torch.equal(o9[:, :8], o8), (compute, cfg is None)
+            err = _report(f"9th channel {compute}", o9[:, 8:9].cpu().numpy(), ref9)
+            assert np.all(err <= tol)
