@@ -27,7 +27,7 @@ from . import api
 
 DECODE_CANDIDATES = [dict(waves_per_cu=w, stage_capacity=c) for w in (4, 8, 12) for c in (512, 1024)]
 BATCH_CANDIDATES = [dict(item_pixels=p, waves_per_cu=w, stage_capacity=c)
-                    for p in (4096, 16384, 65536) for w in (8, 12) for c in (512, 1024)]
+                    for p in (2048, 4096, 8192, 16384) for w in (8, 12) for c in (512, 1024)]
 
 
 def default_cache_path() -> str:

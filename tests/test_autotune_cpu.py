@@ -16,7 +16,16 @@ def test_cache_round_trip(tmp_path):
 def test_signature_depends_on_content():
     a = T._sig([[1, 2], [3]])
     assert a == T._sig([[1, 2], [3]]) and a != T._sig([[3], [1, 2]])
-    assert len(T.BATCH_CANDIDATES) == 12 and len(T.DECODE_CANDIDATES) == 6
+    assert len(T.DECODE_CANDIDATES) == 6
+
+
+def test_batch_candidates_are_valid_and_distinct():
+    # the library accepts work items of 64..65536 pixels in multiples of 64
+    keys = set()
+    for c in T.BATCH_CANDIDATES:
+        assert 64 <= c["item_pixels"] <= 65536 and c["item_pixels"] % 64 == 0
+        keys.add(tuple(sorted(c.items())))
+    assert len(keys) == len(T.BATCH_CANDIDATES)
 
 
 def test_cache_path_env(monkeypatch, tmp_path):
