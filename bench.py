@@ -113,8 +113,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["f16", "f32", "fp8", "bf16", "varA", "out9", "filtered", "bwd", "qat", "batched",
-                                       "copy"],
+    ap.add_argument("--only", choices=["f16", "f32", "fp8", "bf16", "rowmajor", "varA", "out9", "filtered", "bwd", "qat",
+                                       "batched", "copy"],
                     default=None,
                     help="run only one leg (for profiling); 'copy' runs a plain 1 GiB device copy that "
                          "calibrates the HBM byte counters")
@@ -188,6 +188,20 @@ def main():
         result["bf16_ms"] = msb
 
     extras = {}
+    if args.only in (None, "rowmajor"):
+        # the same samples in row-major pixel order: spans are 256-pixel runs
+        # of one image row instead of four 8x8 tiles
+        log("[bench] FP16 matrix-core decode, row-major pixel order")
+        perm = I.tiled_to_rowmajor(wl.out_w, wl.out_h)
+        uv_rm = np.empty_like(uv)
+        uv_rm[perm] = uv
+        uvt_rm = torch.from_numpy(uv_rm).to(dev)
+        ms_rm = time_launches(lambda: ntc.decode(lat, mlp, uvt_rm, compute="f16", packed=p16, out=out), args.steps,
+                              args.warmup)
+        extras["rowmajor_f16"] = {"Gtexel_per_s": N / (ms_rm * 1e-3) / 1e9, "ms": ms_rm,
+                                  "frac_fp16_mfma": flops / (ms_rm * 1e-3) / 1e12 / PEAK_FP16_TFLOPS,
+                                  "order": "row-major (same uv per pixel as the tiled headline)"}
+        del uvt_rm
     if args.only in (None, "varA") and not args.no_extras:
         # latent layout variant A of the paper: levels at W, W, W/2, W/2
         log("[bench] FP16 decode, latent layout variant A (4096^2, 4096^2, 2048^2, 2048^2)")
@@ -302,6 +316,7 @@ def main():
         best, table = ntc.autotune.tune_batched(mats, cache=None)
         plan = ntc.BatchPlan(mats, ntc.batch_cfg(n_cus=ntc.api._device_cus(dev), **best))
         npx = sum(sp.n for sp in specs)
+        flops_b = sum(algorithmic_flops_per_px(sp.dims) * sp.n for sp in specs)
         ms_one = time_launches(plan.launch, 5, 2)
         g = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
@@ -322,6 +337,9 @@ def main():
                                 "per_material_launches_ms": ms_many,
                                 "Gtexel_per_s": npx / ms_graph / 1e6,
                                 "per_material_Gtexel_per_s": npx / ms_many / 1e6,
+                                "flops": flops_b,
+                                "frac_fp16_mfma": flops_b / (ms_graph * 1e-3) / 1e12 / PEAK_FP16_TFLOPS,
+                                "per_material_frac_fp16_mfma": flops_b / (ms_many * 1e-3) / 1e12 / PEAK_FP16_TFLOPS,
                                 "waves": plan.header()["n_waves"], "autotuned": best,
                                 "autotune_ms": {json.dumps(c, sort_keys=True): round(ms, 3) for c, ms in table}}
         del plan

@@ -137,12 +137,19 @@ ntc_status ntc_mlp_pack_size(const ntc_mlp *mlp, int32_t compute, size_t *bytes)
  * and biases absorb the powers of two, so the network is unchanged); the
  * decode then applies ReLU as the [0, 1] clamp of the FP16 conversion on
  * spans whose coordinates lie in the unit square, and the max-based ReLU
- * elsewhere. If a bound exceeds 2^10 the image is left unscaled and every
- * span uses the max-based ReLU.
- * For NTC_FP8_E4M3, per-layer scales s_w = 448 / max|W_l| are computed on
- * the device and act_amax [device, n_layers floats] must hold the largest
- * |input| of every layer (see ntc_calibrate_fp8); s_a = 448 / act_amax[l].
- * Otherwise act_amax is ignored. packed [device, 256-byte aligned]. */
+ * elsewhere. The output layer keeps e = 0, so its weights take the factor
+ * 2^e of their input neuron; if a bound exceeds 2^10, or a scaled output
+ * weight would exceed 2^15 (FP16 holds at most 65504), the image is left
+ * unscaled and every span uses the max-based ReLU.
+ * For NTC_FP8_E4M3, per-layer scales are powers of two computed on the
+ * device: s_w = 2^floor(log2(448 / max|W_l|)) and
+ * s_a = 2^floor(log2(448 / act_amax[l])), so that scaled values stay within
+ * E4M3's +-448 and the factor that maps a layer's accumulator to the next
+ * layer's scaled input is itself a power of two (the decode applies it as
+ * the matrix instruction's E8M0 block scale). act_amax [device, n_layers
+ * floats] must hold the largest |input| of every layer (see
+ * ntc_calibrate_fp8). Otherwise act_amax is ignored. packed [device,
+ * 256-byte aligned]. */
 ntc_status ntc_mlp_pack(const ntc_mlp *mlp, int32_t compute, const float *act_amax,
                         void *packed, size_t bytes, void *stream);
 
@@ -214,9 +221,11 @@ typedef struct {
  *     by the fraction of lod;
  *   NTC_FILTER_ANISOTROPIC: N = min(ceil(Pmax / Pmin), max_aniso) trilinear
  *     samples at lod = log2(Pmax / N) along the longer axis, at
- *     uv + (i / (N + 1) - 1/2) (du, dv) for i = 1..N, averaged. N is the
- *     smallest n with n^2 Pmin^2 >= Pmax^2, with the squared lengths and that
- *     product rounded as FP32 operations in this order (no fused multiply-add).
+ *     uv + (i / (N + 1) - 1/2) (du, dv) for i = 1..N, averaged. N is
+ *     decided in FP32 as the smallest n with n^2 Pmin^2 >= Pmax^2, the
+ *     squared lengths and that product rounded as FP32 operations (no fused
+ *     multiply-add); this is min(ceil(Pmax / Pmin), max_aniso) except where
+ *     Pmax / Pmin lies within FP32 rounding of an integer.
  * max_aniso in 1..NTC_MAX_ANISO. packed is the NTC_F16 image of mlp; uv,
  * out and out_dtype as for ntc_decode. */
 ntc_status ntc_decode_filtered(const ntc_latent_mips *lat, const ntc_mlp *mlp, const void *packed, const float *uv,

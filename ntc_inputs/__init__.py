@@ -28,7 +28,7 @@ __all__ = [
     "streams", "bc1_level", "bc1_pyramid", "f32_pyramid", "xavier_mlp",
     "pixel_uv", "pixel_uv_subset", "random_uv", "value_noise_texture",
     "point_sample", "Workload", "WORKLOADS", "make_workload", "material_specs",
-    "MaterialSpec", "make_material", "TILE",
+    "MaterialSpec", "make_material", "TILE", "tiled_to_rowmajor",
 ]
 
 # Pixels are laid out in square tiles of TILE x TILE screen pixels (row-major
@@ -111,6 +111,13 @@ def _pixel_xy(width: int, height: int, order: str) -> Tuple[np.ndarray, np.ndarr
         t, r = k // (TILE * TILE), k % (TILE * TILE)
         return (t % tiles_x) * TILE + r % TILE, (t // tiles_x) * TILE + r // TILE
     raise ValueError(order)
+
+
+def tiled_to_rowmajor(width: int, height: int) -> np.ndarray:
+    """int64 [W*H]: the row-major index y W + x of the k-th pixel in tiled
+    order (so ``a_rowmajor[perm] = a_tiled`` reorders per-pixel arrays)."""
+    x, y = _pixel_xy(width, height, "tiled")
+    return y * width + x
 
 
 def pixel_uv(width: int, height: int, order: str = "rowmajor",

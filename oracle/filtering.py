@@ -16,10 +16,14 @@ texture-filtering definitions):
   * anisotropic: N = min(ceil(Pmax / Pmin), max_aniso) trilinear samples at
     lod = log2(Pmax / N) along the longer axis, at uv + (i/(N + 1) - 1/2) d
     for i = 1..N, averaged;
-  * N is an integer decided by floating point, so it is taken exactly as the
-    kernel takes it: the smallest n with n^2 Pmin^2 >= Pmax^2, the squared
-    lengths and the product rounded as FP32 operations (numpy float32 does
-    not fuse them). Everything else is FP64.
+  * N is the smallest integer n >= 1 with n Pmin >= Pmax (so ceil of the
+    axis ratio, 1 for a zero footprint and max_aniso for a degenerate one),
+    decided in FP64 like everything else here: the squared lengths of the
+    FP32 derivatives times power-of-two sizes are exact in FP64 up to one
+    rounding of their sum, so the decision is the mathematical one except
+    for ratios within about 1e-16 of an integer. A kernel that decides N in
+    FP32 can only differ from it where the ratio lies within FP32 rounding
+    of an integer.
 """
 from __future__ import annotations
 
@@ -28,20 +32,32 @@ import numpy as np
 import oracle as O
 
 
-def axes_sq_f32(duv: np.ndarray, w0: int, h0: int):
-    """(Px^2, Py^2) as FP32, each operation rounded once."""
-    d = np.asarray(duv, np.float32)
-    w, h = np.float32(w0), np.float32(h0)
-    ax, bx, ay, by = d[:, 0] * w, d[:, 1] * h, d[:, 2] * w, d[:, 3] * h
+def axes_sq(duv: np.ndarray, w0: int, h0: int):
+    """(Px^2, Py^2) in FP64: squared footprint axes in texels of mip 0."""
+    d = np.asarray(duv, np.float64)
+    ax, bx, ay, by = d[:, 0] * w0, d[:, 1] * h0, d[:, 2] * w0, d[:, 3] * h0
     return ax * ax + bx * bx, ay * ay + by * by
 
 
 def aniso_count(px2: np.ndarray, py2: np.ndarray, max_aniso: int) -> np.ndarray:
+    """N = min(ceil(Pmax / Pmin), max_aniso): the smallest n >= 1 with
+    n^2 Pmin^2 >= Pmax^2 (1 when both axes are 0, max_aniso when only Pmin
+    is), compared in FP64."""
+    px2 = np.asarray(px2, np.float64)
+    py2 = np.asarray(py2, np.float64)
     pmax2, pmin2 = np.maximum(px2, py2), np.minimum(px2, py2)
     n = np.full(px2.shape, max_aniso, np.int64)
     for i in range(max_aniso - 1, 0, -1):
-        n = np.where(np.float32(i * i) * pmin2 >= pmax2, i, n)
+        n = np.where(float(i * i) * pmin2 >= pmax2, i, n)
     return n
+
+
+def aniso_ratio(px2: np.ndarray, py2: np.ndarray) -> np.ndarray:
+    """Pmax / Pmin in FP64 (inf for Pmin = 0, nan for a zero footprint)."""
+    pmax2 = np.maximum(px2, py2).astype(np.float64)
+    pmin2 = np.minimum(px2, py2).astype(np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.sqrt(pmax2 / pmin2)
 
 
 def _log2(x):
@@ -79,7 +95,7 @@ def level_features(chain, shift, uv: np.ndarray, duv: np.ndarray, filt: str, max
     duv = np.asarray(duv, np.float64)
     h0, w0 = chain[0].shape[0] * 4, chain[0].shape[1] * 4
     top = len(chain) - 1
-    px2, py2 = axes_sq_f32(duv, w0, h0)
+    px2, py2 = axes_sq(duv, w0, h0)
     if filt == "trilinear":
         lod = np.clip(0.5 * _log2(np.maximum(px2, py2)), 0.0, top)
         return trilinear(chain, shift, lod, uv)

@@ -192,6 +192,19 @@ __global__ __launch_bounds__(64) void pack_bounds_kernel(PackArgs a) {
     ex[l * 64 + i] = e;
     __syncthreads();
   }
+  // The output layer keeps e = 0, so its weights take the whole factor
+  // 2^e(j) of their input neuron j: the image is only usable if every such
+  // weight stays finite in FP16 (|W| 2^e(j) <= 2^15 < 65504, leaving room
+  // for the conversion's rounding); otherwise it stays unscaled.
+  {
+    const int rows = a.p.dims[Ln], cols = a.p.dims[Ln - 1];
+    if (i < cols) {
+      double m = 0.0;
+      for (int r = 0; r < rows; ++r) m = fmax(m, fabs((double)a.p.W[Ln - 1][(int64_t)r * cols + i]));
+      if (!(ldexp(m, e_prev[i]) <= 32768.0)) bad = 1;
+    }
+    __syncthreads();
+  }
   const bool ok = bad == 0;
   for (int l = Ln - 1; l < kMaxLayers; ++l) ex[l * 64 + i] = 0;
   if (!ok)

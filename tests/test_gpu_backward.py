@@ -3,10 +3,12 @@ central finite differences of the oracle loss (h = 1e-3).
 
 Where floating point takes a branch (the ReLU derivative), the FP32 kernel
 and the FP64 oracle can disagree for samples whose pre-activation lies
-within rounding distance of zero. Those samples are identified by the
-oracle (smallest |pre-activation| below 1e-4) and given a zero upstream
-gradient on both sides, so every remaining contribution is unique; the
-ambiguous samples are at most a few per million.
+within FP32 rounding distance of zero. Those samples are found with a
+rigorous bound on |z_fp32 - z| per hidden unit (tests/fp32_bounds.py) and
+given a zero upstream gradient on both sides (or left out), so every
+remaining contribution is unique. On the C3 workload the bound leaves out
+about 0.17 % of the samples (1,752 of 2^20); the tests print the count and
+assert that it stays below 0.5 %.
 """
 import numpy as np
 import pytest
@@ -14,10 +16,11 @@ import torch
 
 import ntc_inputs as I
 import oracle as O
+from fp32_bounds import relu_ambiguous
 
 pytestmark = pytest.mark.gpu
 
-MARGIN = 1e-4
+AMBIGUOUS_MAX_FRACTION = 5e-3
 
 
 def _ntc():
@@ -44,9 +47,9 @@ def _gpu_autograd(lat_np, Ws, bs, uv, tgt, shift):
             [t.grad.cpu().numpy() for t in lat_t], out.detach().cpu().numpy())
 
 
-def _gpu_direct(lat_np, Ws, bs, uv, g, shift):
+def _gpu_direct(lat_np, Ws, bs, uv, g, shift, address="clamp"):
     ntc = _ntc()
-    lat = ntc.Latents(lat_np, shift=shift)
+    lat = ntc.Latents(lat_np, shift=shift, address=address)
     mlp = ntc.Mlp(Ws, bs)
     gW, gb, gl = ntc.decode_backward(lat, mlp, torch.from_numpy(uv).cuda(),
                                      torch.from_numpy(g.astype(np.float32)).cuda())
@@ -60,8 +63,10 @@ def test_backward_autograd_small():
     Ws, bs = I.xavier_mlp(rng, (14, 64, 64, 8), bias="normal")
     uv = I.random_uv(rng, 4099)
     olat, omlp = O.Latents(lat_np, shift=I.PAPER_SHIFT), O.Mlp(Ws, bs)
-    keep = O.relu_margin(olat, omlp, uv) >= MARGIN
-    uv = uv[keep]
+    amb = relu_ambiguous(olat, Ws, bs, uv, lat_np)
+    print(f"[small] ambiguous samples: {int(amb.sum())} of {uv.shape[0]}", flush=True)
+    assert amb.sum() <= AMBIGUOUS_MAX_FRACTION * uv.shape[0]
+    uv = uv[~amb]
     tgt = rng.random((uv.shape[0], 8)).astype(np.float32)
     gW, gb, gl, f = _gpu_autograd(lat_np, Ws, bs, uv, tgt, I.PAPER_SHIFT)
     of = O.decode(olat, omlp, uv)
@@ -74,14 +79,42 @@ def test_backward_autograd_small():
         _close(f"dlat{k}", gl[k], ol[k])
 
 
+def test_backward_wrap_addressing():
+    """Wrap addressing with uv in [-0.5, 1.5): taps that leave a level wrap
+    around, and their gradients land on the texels of the opposite edge;
+    against the oracle's wrap-mode backward."""
+    rng = np.random.default_rng(37)
+    sizes = [(32, 32), (16, 16), (8, 8), (4, 4)]
+    lat_np = I.f32_pyramid(rng, sizes)
+    Ws, bs = I.xavier_mlp(rng, (14, 32, 32, 8), bias="normal")
+    uv = (rng.random((6000, 2)) * 2.0 - 0.5).astype(np.float32)
+    olat = O.Latents(lat_np, shift=I.PAPER_SHIFT, address=O.WRAP)
+    omlp = O.Mlp(Ws, bs)
+    amb = relu_ambiguous(olat, Ws, bs, uv, lat_np)
+    print(f"[wrap] ambiguous samples: {int(amb.sum())} of {uv.shape[0]}", flush=True)
+    assert amb.sum() <= AMBIGUOUS_MAX_FRACTION * uv.shape[0]
+    g = rng.standard_normal((uv.shape[0], 8)) * 1e-3
+    g[amb] = 0.0
+    g = g.astype(np.float32).astype(np.float64)
+    gW, gb, gl = _gpu_direct(lat_np, Ws, bs, uv, g, I.PAPER_SHIFT, address="wrap")
+    oW, ob, ol = O.backward(olat, omlp, uv, g)
+    for l in range(3):
+        _close(f"wrap dW{l}", gW[l], oW[l])
+        _close(f"wrap db{l}", gb[l], ob[l])
+    for k in range(4):
+        _close(f"wrap dlat{k}", gl[k], ol[k])
+    # every edge texel of level 0 receives gradient from wrapped taps
+    assert np.all(ol[0][0] != 0) and np.all(ol[0][:, 0] != 0)
+
+
 @pytest.fixture(scope="module")
 def c3():
     wl = I.WORKLOADS["c3"]
     lat_np, Ws, bs, uv = I.make_workload(wl)
     tgt = I.point_sample(I.c3_targets(), uv)
     olat, omlp = O.Latents(lat_np, shift=wl.shift), O.Mlp(Ws, bs)
-    margin = O.relu_margin(olat, omlp, uv)
-    return dict(wl=wl, lat_np=lat_np, Ws=Ws, bs=bs, uv=uv, tgt=tgt, olat=olat, omlp=omlp, margin=margin)
+    amb = relu_ambiguous(olat, Ws, bs, uv, lat_np)
+    return dict(wl=wl, lat_np=lat_np, Ws=Ws, bs=bs, uv=uv, tgt=tgt, olat=olat, omlp=omlp, amb=amb)
 
 
 def test_backward_c3_full_size(c3):
@@ -90,8 +123,9 @@ def test_backward_c3_full_size(c3):
     uv, tgt = c3["uv"], c3["tgt"]
     f = O.decode(c3["olat"], c3["omlp"], uv)
     g = (2.0 * (f - tgt) / f.size).astype(np.float32).astype(np.float64)
-    amb = c3["margin"] < MARGIN
+    amb = c3["amb"]
     print(f"[c3] ambiguous samples: {int(amb.sum())} of {uv.shape[0]}", flush=True)
+    assert amb.sum() <= AMBIGUOUS_MAX_FRACTION * uv.shape[0]
     g[amb] = 0.0
     gW, gb, gl = _gpu_direct(c3["lat_np"], c3["Ws"], c3["bs"], uv, g, c3["wl"].shift)
     oW, ob, ol = O.backward(c3["olat"], c3["omlp"], uv, g)
@@ -108,7 +142,7 @@ def test_backward_c3_finite_differences(c3):
     against the GPU gradient from the autograd path, on 16384 of the samples."""
     rng = np.random.default_rng(33)
     sel = np.sort(rng.choice(c3["uv"].shape[0], 16384, replace=False))
-    sel = sel[c3["margin"][sel] >= MARGIN]
+    sel = sel[~c3["amb"][sel]]
     uv, tgt = c3["uv"][sel], c3["tgt"][sel]
     lat_np, Ws, bs = c3["lat_np"], c3["Ws"], c3["bs"]
     shift = c3["wl"].shift

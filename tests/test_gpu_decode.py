@@ -2,8 +2,10 @@
 
 Gates: BC1 texel decode bit-exact; outputs within 1e-5 relative (FP32),
 2e-3 absolute (FP16) and 3e-2 absolute (FP8 E4M3) of the exact FP64 result.
-Full-size workloads (4096^2 pixels) are checked on sampled pixels, computed
-one by one by the oracle; small workloads on every pixel.
+Full-size workloads (4096^2 pixels) are checked on every pixel against the
+oracle's decode of the whole image (a few seconds on the host's cores), in
+the benchmark's 8x8-tile pixel order and in row-major order; small workloads
+on every pixel too.
 """
 import numpy as np
 import pytest
@@ -216,6 +218,89 @@ def test_f16_large_bounds_parity():
     assert torch.equal(out, direct)
 
 
+def test_f16_scaled_output_weights_stay_finite():
+    """A hidden neuron whose bound needs the largest scale (bias 700: 2^-10)
+    and whose outgoing weights are 100: scaled, those weights would be
+    102400, beyond FP16's finite range, and the neuron's zero outputs would
+    turn the outputs into NaN (0 * inf). The packer leaves such an image
+    unscaled: parity with the oracle on every pixel, no NaN.
+
+    The neuron reads level 0's red channel only (weight -1400): the level is
+    red (1) on its left half and black (0) on its right half and the samples
+    sit on its texel centres, so the neuron is 700 (on) or -700 (off) exactly
+    and its large output weights never meet a small activation."""
+    ntc = _ntc()
+    rng = np.random.default_rng(34)
+    red = np.uint64(0xF800 | (0xF800 << 16))
+    lvl0 = np.zeros((16, 16), np.uint64)
+    lvl0[:, :8] = red
+    lat_np = [lvl0] + I.bc1_pyramid(rng, [(32, 32), (16, 16), (8, 8)])
+    Ws, bs = I.xavier_mlp(rng, (14, 32, 8), bias="normal")
+    Ws[0][0, :] = 0.0
+    Ws[0][0, 0] = -1400.0
+    bs[0][0] = 700.0
+    Ws[1][:, 0] = 0.001
+    Ws[1][3, 0] = 100.0
+    shift = ((0.0, 0.0), (0.5, 0.5), (0.0, 0.0), (0.5, 0.5))
+    uv = I.pixel_uv(64, 64, order="tiled")
+    lat, mlp = _gpu_case(lat_np, Ws, bs, shift)
+    uvt = torch.from_numpy(uv).cuda()
+    olat, omlp = _oracle_case(lat_np, Ws, bs, shift)
+    ref = O.decode(olat, omlp, uv)
+    x0 = O.features(olat, uv)[:, 0]
+    assert set(np.unique(x0)) == {0.0, 1.0}
+    for cfg in (None, ntc.tile_cfg(stage_capacity=64)):
+        out = ntc.decode(lat, mlp, uvt, compute="f16", cfg=cfg)
+        assert torch.isfinite(out).all()
+        err = _report("f16 large output weights", out.cpu().numpy(), ref)
+        assert np.all(err <= TOL_F16_ABS)
+
+
+def test_non_finite_and_far_uv():
+    """uv outside the unit square: NaN, +-inf and huge finite values. The
+    sampling position is limited before the taps are formed (NaN to the left
+    or top edge, everything else clamped to the edge texels), so no access
+    leaves a level; u and v themselves are features, so the outputs of
+    non-finite samples are not specified. Finite samples of the same launch
+    equal a launch without the others bit for bit on every path (FP32, FP16,
+    E4M3; staged and direct); huge finite coordinates with zero weights on
+    the u, v features decode to the edge texels (FP32 path, against the
+    oracle)."""
+    ntc = _ntc()
+    rng = np.random.default_rng(36)
+    lat_np = I.bc1_pyramid(rng, [(64, 64), (32, 32), (16, 16), (8, 8)])
+    Ws, bs = I.xavier_mlp(rng, (14, 32, 32, 8), bias="normal")
+    Ws[0][:, 12:] = 0.0
+    lat, mlp = _gpu_case(lat_np, Ws, bs, I.PAPER_SHIFT)
+    clean = rng.random((1000, 2)).astype(np.float32)
+    bad = np.array([[np.nan, 0.5], [0.5, np.nan], [np.inf, 0.2], [-np.inf, 0.7], [0.3, np.inf],
+                    [0.6, -np.inf], [np.nan, np.nan], [np.inf, -np.inf]], np.float32)
+    far = np.array([[1e10, 0.5], [-1e10, 0.25], [0.5, 3e38], [0.75, -3e38], [-3e38, 3e38], [2.5, -1.5]],
+                   np.float32)
+    mixed = np.concatenate([clean[:300], bad, clean[300:600], far, clean[600:]])
+    is_clean = np.ones(mixed.shape[0], bool)
+    is_clean[300:300 + len(bad)] = False
+    is_clean[600 + len(bad):600 + len(bad) + len(far)] = False
+    cal = torch.from_numpy(I.calibration_uv(4096)).cuda()
+    p8 = ntc.pack(mlp, "fp8", act_amax=ntc.calibrate_fp8(lat, mlp, cal))
+    for compute, packed in (("f32", None), ("f16", None), ("fp8", p8)):
+        for cfg in (None, ntc.tile_cfg(stage_capacity=64)):
+            if compute == "f32" and cfg is not None:
+                continue
+            a = ntc.decode(lat, mlp, torch.from_numpy(mixed).cuda(), compute=compute, packed=packed, cfg=cfg)
+            b = ntc.decode(lat, mlp, torch.from_numpy(clean).cuda(), compute=compute, packed=packed, cfg=cfg)
+            torch.cuda.synchronize()
+            assert torch.equal(a[torch.from_numpy(is_clean).cuda()], b), (compute, cfg is None)
+    out = ntc.decode(lat, mlp, torch.from_numpy(far).cuda(), compute="f32").cpu().numpy()
+    olat, omlp = _oracle_case(lat_np, Ws, bs, I.PAPER_SHIFT)
+    # the oracle clamps each tap; the kernel limits the position first: the
+    # same edge texels either way
+    edge = np.clip(far.astype(np.float64), -4.0, 4.0)
+    ref = O.decode(olat, omlp, edge)
+    err = _report("far uv f32", out, ref)
+    assert np.all(err <= TOL_F32_REL * np.abs(ref))
+
+
 def test_random_uv_fallback_parity():
     """Random uv: tile footprints exceed the staging capacity -> direct fetches."""
     ntc = _ntc()
@@ -248,7 +333,7 @@ def test_empty_and_out_f16():
 
 
 # ---------------------------------------------------------------------------
-# Full-size workloads (4096^2 pixels), sampled parity
+# Full-size workloads (4096^2 pixels), every pixel
 # ---------------------------------------------------------------------------
 @pytest.fixture(scope="module")
 def c2_case():
@@ -258,30 +343,53 @@ def c2_case():
     lat, mlp = _gpu_case(lat_np, Ws, bs, wl.shift)
     uvt = torch.from_numpy(uv).cuda()
     olat, omlp = _oracle_case(lat_np, Ws, bs, wl.shift)
+    print(f"\n[c2] oracle over all {uv.shape[0]} pixels", flush=True)
+    ref = O.decode(olat, omlp, uv)
     idx = _sample_index(uv.shape[0], 30000, 7)
-    ref = O.decode_index(olat, omlp, uv, idx)
     return dict(wl=wl, lat_np=lat_np, Ws=Ws, bs=bs, uv=uv, lat=lat, mlp=mlp, uvt=uvt, olat=olat, omlp=omlp,
                 idx=idx, ref=ref)
 
 
-def test_c2_f16_full_size_sampled(c2_case):
+def _check_all(name, out, ref, tol=None, rel=None):
+    """Every pixel against the oracle (absolute gate `tol` or relative `rel`)."""
+    assert torch.isfinite(out).all(), name
+    err = _report(name, out.cpu().numpy(), ref)
+    if tol is not None:
+        assert np.all(err <= tol), name
+    if rel is not None:
+        assert np.all(err <= rel * np.abs(ref)), name
+    return err
+
+
+def test_c2_f16_full_size(c2_case):
     ntc = _ntc()
     c = c2_case
     out = ntc.decode(c["lat"], c["mlp"], c["uvt"], compute="f16")
-    got = out[torch.from_numpy(c["idx"]).cuda()].cpu().numpy()
-    err = _report("c2 f16 4096^2", got, c["ref"])
-    assert np.all(err <= TOL_F16_ABS)
-    assert torch.isfinite(out).all()
+    _check_all("c2 f16 4096^2 all pixels", out, c["ref"], tol=TOL_F16_ABS)
 
 
-def test_c2_bf16_full_size_sampled(c2_case):
+def test_c2_f16_rowmajor_full_size(c2_case):
+    """The same 16.7 M samples in row-major pixel order (spans are 256-pixel
+    runs of one row instead of four 8x8 tiles): every pixel against the
+    oracle, and bit for bit the tiled launch's result for the same sample."""
+    ntc = _ntc()
+    c = c2_case
+    perm = I.tiled_to_rowmajor(4096, 4096)
+    uv_rm = np.empty_like(c["uv"])
+    uv_rm[perm] = c["uv"]
+    ref_rm = np.empty_like(c["ref"])
+    ref_rm[perm] = c["ref"]
+    out_rm = ntc.decode(c["lat"], c["mlp"], torch.from_numpy(uv_rm).cuda(), compute="f16")
+    _check_all("c2 f16 4096^2 row-major all pixels", out_rm, ref_rm, tol=TOL_F16_ABS)
+    out_t = ntc.decode(c["lat"], c["mlp"], c["uvt"], compute="f16")
+    assert torch.equal(out_rm[torch.from_numpy(perm).cuda()], out_t)
+
+
+def test_c2_bf16_full_size(c2_case):
     ntc = _ntc()
     c = c2_case
     out = ntc.decode(c["lat"], c["mlp"], c["uvt"], compute="bf16")
-    got = out[torch.from_numpy(c["idx"]).cuda()].cpu().numpy()
-    err = _report("c2 bf16 4096^2", got, c["ref"])
-    assert np.all(err <= TOL_BF16_ABS)
-    assert torch.isfinite(out).all()
+    _check_all("c2 bf16 4096^2 all pixels", out, c["ref"], tol=TOL_BF16_ABS)
 
 
 def test_varA_layout_parity():
@@ -306,16 +414,28 @@ def test_varA_layout_parity():
         assert torch.equal(out, direct)
 
 
-def test_c2_f32_full_size_sampled(c2_case):
+def test_c2_f32_full_size(c2_case):
     ntc = _ntc()
     c = c2_case
     out = ntc.decode(c["lat"], c["mlp"], c["uvt"], compute="f32")
-    got = out[torch.from_numpy(c["idx"]).cuda()].cpu().numpy()
-    err = _report("c2 f32 4096^2", got, c["ref"])
-    assert np.all(err <= TOL_F32_REL * np.abs(c["ref"]))
+    _check_all("c2 f32 4096^2 all pixels", out, c["ref"], rel=TOL_F32_REL)
 
 
-def test_c4_fp8_full_size_sampled(c2_case):
+# E4M3 against the oracle's E4M3 emulation (same scales, same roundings of
+# weights and activations, exact accumulation). The two differ where an FP32
+# accumulation lands on the other side of an E4M3 rounding midpoint than the
+# exact sum: a pre-activation z evaluated by FP32 fused multiply-adds is off
+# by at most about n u sum|terms| (n <= 64, u = 2^-24), i.e. within ~4e-6 of
+# sum|terms|, while midpoints of E4M3 sit 2^-4 .. 2^-3 of the value apart, so
+# with sum|terms| / |z| of order 10 a conversion flips with probability
+# below 2 * 4e-6 * 10 / 2^-4 ~ 1.3e-3 and a pixel (206 conversions) rarely
+# sees more than one. Pixels without a flip agree to FP32 rounding; a flip
+# moves one activation by one E4M3 step, which the gate tolerates.
+FP8_EMU_MATCH_TOL = 1e-4
+FP8_EMU_MIN_MATCH = 0.9
+
+
+def test_c4_fp8_full_size(c2_case):
     ntc = _ntc()
     c = c2_case
     cal = torch.from_numpy(I.calibration_uv()).cuda()
@@ -325,15 +445,17 @@ def test_c4_fp8_full_size_sampled(c2_case):
     assert np.allclose(amax.cpu().numpy(), oam, rtol=1e-5)
     packed = ntc.pack(c["mlp"], "fp8", act_amax=amax)
     out = ntc.decode(c["lat"], c["mlp"], c["uvt"], compute="fp8", packed=packed)
+    _check_all("c4 fp8 4096^2 all pixels", out, c["ref"], tol=TOL_FP8_ABS)
     got = out[torch.from_numpy(c["idx"]).cuda()].cpu().numpy()
-    err = _report("c4 fp8 4096^2", got, c["ref"])
-    assert np.all(err <= TOL_FP8_ABS)
-    # diagnostic: the oracle with the same E4M3 rounding and scales
     ws, as_ = O.fp8_scales(c["Ws"], oam, pow2=True)
     emu = O.decode_index(c["olat"], O.Mlp(c["Ws"], c["bs"], precision=O.FP8, w_scale=ws, a_scale=as_), c["uv"],
                          c["idx"])
-    d = np.abs(got - emu)
-    print(f"[c4 fp8 vs emulation] max {d.max():.3g} rms {np.sqrt((d**2).mean()):.3g}", flush=True)
+    d = np.abs(got - emu).max(axis=1)
+    match = float(np.mean(d <= FP8_EMU_MATCH_TOL))
+    print(f"[c4 fp8 vs emulation] max {d.max():.3g} rms {np.sqrt((d**2).mean()):.3g} "
+          f"pixels within {FP8_EMU_MATCH_TOL:g}: {match:.4f}", flush=True)
+    assert match >= FP8_EMU_MIN_MATCH
+    assert d.max() <= TOL_FP8_ABS
 
 
 def test_extra_output_row_keeps_other_channels_bit_identical():

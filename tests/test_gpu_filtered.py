@@ -1,8 +1,11 @@
 """Filtered decode over BC1 mip chains (ntc_decode_filtered; Sec. 3.2 mip
 chains, Sec. 3.3 trilinear / anisotropic fetches) against the FP64 oracle
-(oracle/filtering.py). The tap count N is an integer both sides decide with
-the same FP32 operations; everything else is continuous in the inputs and
-held to the FP16 gate."""
+(oracle/filtering.py). The tap count N is an integer: the oracle takes the
+exact N = min(ceil(Pmax / Pmin), max_aniso) (FP64), the kernel decides it
+with FP32 squared lengths, so the two can differ only for samples whose axis
+ratio lies within FP32 rounding of an integer below max_aniso. Those
+samples (counted and printed, at most 0.1 %) are left out of the comparison;
+everything else is continuous in the inputs and held to the FP16 gate."""
 import numpy as np
 import pytest
 import torch
@@ -14,6 +17,24 @@ from oracle import filtering as F
 pytestmark = pytest.mark.gpu
 
 TOL_F16_ABS = 2e-3
+# relative distance of the axis ratio from an integer within which the FP32
+# decision of N may differ from the exact one: the FP32 squared lengths carry
+# at most 3 roundings each (2 products, 1 sum: 3u), their product with i^2
+# one more, so the compared ratio^2 is off by < 8u and the ratio by < 4u
+# (u = 2^-24); 1e-6 leaves a factor 4 of headroom
+RATIO_TOL = 1e-6
+
+
+def _ambiguous(levels_wh, duv, max_aniso):
+    """Samples whose tap count the FP32 decision may take differently on
+    some level: ratio within RATIO_TOL of an integer 1 .. max_aniso - 1."""
+    amb = np.zeros(duv.shape[0], bool)
+    for (w, h) in levels_wh:
+        r = F.aniso_ratio(*F.axes_sq(duv, w, h))
+        k = np.round(r)
+        with np.errstate(invalid="ignore"):
+            amb |= (k >= 1) & (k <= max_aniso - 1) & (np.abs(r - k) <= RATIO_TOL * k)
+    return amb
 
 
 def _ntc():
@@ -54,10 +75,13 @@ def test_perspective_plane_parity(filt, max_aniso):
                               torch.from_numpy(uv).cuda(), torch.from_numpy(duv).cuda(), filter=filt,
                               max_aniso=max_aniso).cpu().numpy()
     ref = F.decode(chains, I.PAPER_SHIFT, O.Mlp(Ws, bs), uv, duv, filt, max_aniso)
-    err = np.abs(out - ref).max()
-    px2, py2 = F.axes_sq_f32(duv, 256, 256)
+    keep = ~_ambiguous(sizes, duv, max_aniso) if filt == "anisotropic" else np.ones(uv.shape[0], bool)
+    err = np.abs(out - ref)[keep].max()
+    px2, py2 = F.axes_sq(duv, 256, 256)
     n = F.aniso_count(px2, py2, max_aniso)
-    print(f"\n[filtered {filt} {max_aniso}] n={uv.shape[0]} taps {np.bincount(n)} max err {err:.2e}", flush=True)
+    print(f"\n[filtered {filt} {max_aniso}] n={uv.shape[0]} taps {np.bincount(n)} "
+          f"left out {int((~keep).sum())} max err {err:.2e}", flush=True)
+    assert (~keep).sum() <= 1e-3 * uv.shape[0]
     assert err <= TOL_F16_ABS
 
 
@@ -75,6 +99,9 @@ def test_random_derivatives_parity():
                                   torch.from_numpy(uv).cuda(), torch.from_numpy(duv).cuda(), filter=filt,
                                   max_aniso=8).cpu().numpy()
         ref = F.decode(chains, I.PAPER_SHIFT, O.Mlp(Ws, bs), uv, duv, filt, 8)
-        err = np.abs(out - ref).max()
-        print(f"[random duv {filt}] max err {err:.2e}", flush=True)
+        keep = ~_ambiguous([(128, 64), (64, 32), (32, 16), (16, 8)], duv, 8) if filt == "anisotropic" \
+            else np.ones(n, bool)
+        err = np.abs(out - ref)[keep].max()
+        print(f"[random duv {filt}] left out {int((~keep).sum())} max err {err:.2e}", flush=True)
+        assert (~keep).sum() <= 1e-3 * n
         assert err <= TOL_F16_ABS, filt

@@ -13,6 +13,7 @@ import torch
 
 import ntc_inputs as I
 import oracle as O
+from fp32_bounds import relu_ambiguous
 from oracle import qat as Q
 
 pytestmark = pytest.mark.gpu
@@ -79,8 +80,12 @@ def test_qat_training_chain():
     # texels exactly as both sides see them
     tex64 = [Q.texels(p)[2] for p in params]
     olat, omlp = O.Latents([t.astype(np.float32) for t in tex64], shift=I.PAPER_SHIFT), O.Mlp(Ws, bs)
-    keep = O.relu_margin(olat, omlp, uv) >= 1e-4
-    uv = uv[keep]
+    # samples on a ReLU kink within FP32 rounding are left out (the FP32 error
+    # bound of tests/fp32_bounds.py)
+    amb = relu_ambiguous(olat, Ws, bs, uv, [t.astype(np.float32) for t in tex64])
+    print(f"[qat chain] ambiguous samples: {int(amb.sum())} of {uv.shape[0]}", flush=True)
+    assert amb.sum() <= 5e-3 * uv.shape[0]
+    uv = uv[~amb]
     tgt = rng.random((uv.shape[0], 8)).astype(np.float32)
 
     p_t = [torch.from_numpy(p).cuda().requires_grad_(True) for p in params]

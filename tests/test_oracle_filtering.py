@@ -57,7 +57,7 @@ def test_trilinear_weights_on_solid_mips():
         m0 = int(np.floor(lod))
         t = lod - m0
         exp = vals[m0] if m0 == 4 else (1 - t) * vals[m0] + t * vals[m0 + 1]
-        assert np.allclose(got[r], exp, atol=1e-6), r   # lod from FP32 squared lengths
+        assert np.allclose(got[r], exp, rtol=0, atol=1e-12), r
 
 
 def test_anisotropic_count_and_lod():
@@ -66,7 +66,7 @@ def test_anisotropic_count_and_lod():
     cols = [0xF800, 0x07E0, 0x001F, 0xFFE0, 0x0000]
     chain = _solid_chain(sizes, cols)
     duv = np.array([[0.0, 2.0 / 64, 8.0 / 64, 0.0]])
-    px2, py2 = F.axes_sq_f32(duv, 64, 64)
+    px2, py2 = F.axes_sq(duv, 64, 64)
     assert F.aniso_count(px2, py2, 16)[0] == 4
     assert F.aniso_count(px2, py2, 3)[0] == 3
     got = F.level_features(chain, SH, np.array([[0.5, 0.5]]), duv, "anisotropic")
@@ -93,12 +93,40 @@ def test_anisotropic_taps_average_trilinear_samples():
     assert np.allclose(got, ref_mip1, rtol=0, atol=1e-15)
 
 
-def test_count_is_ceil_of_ratio_away_from_integers():
+def test_count_is_ceil_of_ratio():
+    """N = min(ceil(Pmax / Pmin), max_aniso) against exact rational
+    arithmetic: derivatives on a 1/64 grid (squared lengths exact), including
+    axes whose ratio is exactly an integer (3-4-5 right triangles), where the
+    count must be that integer and not the next."""
+    from fractions import Fraction
     rng = np.random.default_rng(4)
+    ints = rng.integers(-40, 41, (4000, 4)).astype(np.float64)
+    exact_pairs = np.array([[3, 4, 0, 5], [6, 8, 3, 4], [0, 9, 3, 0], [12, 16, 0, 5], [5, 0, 0, 1],
+                            [0, 0, 0, 0], [0, 0, 7, 0], [16, 0, 0, 1], [17, 0, 0, 1], [30, 40, 3, 4]], np.float64)
+    ints = np.concatenate([exact_pairs, ints])
+    duv = ints / 64.0
+    px2, py2 = F.axes_sq(duv, 64, 64)
+    for max_aniso in (16, 4):
+        n = F.aniso_count(px2, py2, max_aniso)
+        for r in range(ints.shape[0]):
+            a = [Fraction(int(v)) for v in ints[r]]
+            p2 = a[0] ** 2 + a[1] ** 2
+            q2 = a[2] ** 2 + a[3] ** 2
+            hi, lo = max(p2, q2), min(p2, q2)
+            k = 1
+            while k < max_aniso and k * k * lo < hi:
+                k += 1
+            assert n[r] == k, (ints[r], max_aniso, n[r], k)
+    n16 = F.aniso_count(px2, py2, 16)
+    assert list(n16[:10]) == [1, 2, 3, 4, 5, 1, 16, 16, 16, 10]
+
+
+def test_count_is_ceil_of_ratio_random():
+    """On random derivatives the count is ceil of the FP64 axis ratio,
+    capped (integer ratios do not occur there)."""
+    rng = np.random.default_rng(5)
     duv = rng.standard_normal((20000, 4)) * 0.05
-    px2, py2 = F.axes_sq_f32(duv, 256, 128)
+    px2, py2 = F.axes_sq(duv, 256, 128)
     n = F.aniso_count(px2, py2, 16)
-    r = np.sqrt(np.maximum(px2, py2).astype(np.float64) / np.minimum(px2, py2))
-    exact = np.minimum(np.ceil(r), 16)
-    far = np.abs(r - np.round(r)) > 1e-5
-    assert np.array_equal(n[far], exact[far])
+    r = F.aniso_ratio(px2, py2)
+    assert np.array_equal(n, np.minimum(np.ceil(r), 16))

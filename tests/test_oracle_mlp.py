@@ -224,3 +224,55 @@ def test_layer_amax(oracle_lib):
     assert am[0] == np.max(np.abs(x))
     h1 = np.maximum(Ws[0].astype(np.float64) @ x.T + bs[0][:, None], 0)
     assert np.isclose(am[1], np.max(h1), rtol=1e-14)
+
+
+def test_mlp_forward_batch_vs_brute_force(oracle_lib):
+    """oracle.mlp_forward on a batch of several samples with odd widths: every
+    row against plain Python dot-product loops (one sample at a time) and the
+    whole batch against numpy composition. Distinct rows with distinct values
+    catch a wrong row stride of the input or output arrays."""
+    import math
+    O = oracle_lib
+    rng = np.random.default_rng(10)
+    for dims in [(5, 7, 3), (14, 9, 11, 6), (8, 13, 13, 13, 16)]:
+        Ws = [rng.standard_normal((dims[l + 1], dims[l])) * 0.6 for l in range(len(dims) - 1)]
+        bs = [rng.standard_normal(dims[l + 1]) * 0.3 for l in range(len(dims) - 1)]
+        x = rng.random((9, dims[0])) * 2.0 - 0.5
+        got = O.mlp_forward(O.Mlp(Ws, bs), x, threads=3)
+        assert got.shape == (9, dims[-1])
+        for s in range(9):
+            h = [float(v) for v in x[s]]
+            for l in range(len(Ws)):
+                z = [float(bs[l][i]) + sum(float(Ws[l][i, j]) * h[j] for j in range(len(h)))
+                     for i in range(dims[l + 1])]
+                h = [max(v, 0.0) for v in z] if l + 1 < len(Ws) else [1.0 / (1.0 + math.exp(-v)) for v in z]
+            assert np.allclose(got[s], h, rtol=1e-13, atol=1e-15), (dims, s)
+        hh = x.T
+        for l in range(len(Ws) - 1):
+            hh = np.maximum(Ws[l] @ hh + bs[l][:, None], 0.0)
+        assert np.allclose(got, expit(Ws[-1] @ hh + bs[-1][:, None]).T, rtol=1e-13, atol=1e-15)
+        # the rows differ, so a stride error could not hide behind equal rows
+        assert len({tuple(np.round(r, 12)) for r in got}) == 9
+
+
+def test_fp8_scales_closed_forms(oracle_lib):
+    """Per-layer E4M3 scales s = 448 / max|.| (weights: largest magnitude of
+    the layer's matrix, negative entries included; activations: the
+    calibrated amax), and their power-of-two form 2^floor(log2(448 / max))."""
+    O = oracle_lib
+    Ws = [np.array([[0.5, -1.0], [0.25, 0.125]]), np.array([[448.0, 1.0]]), np.array([[-2.0, 500.0]]),
+          np.array([[3.0, -7.0]])]
+    amax = [0.7, 1.0, 448.0, 0.001]
+    ws, as_ = O.fp8_scales(Ws, amax)
+    assert ws[0] == 448.0 and ws[1] == 1.0
+    assert ws[2] == np.float64(np.float32(448.0) / np.float32(500.0))
+    assert ws[3] == 64.0
+    assert as_[0] == np.float64(np.float32(448.0) / np.float32(0.7))
+    assert abs(as_[0] - 640.0) <= 640.0 * 2.0 ** -23
+    assert as_[1] == 448.0 and as_[2] == 1.0
+    assert as_[3] == np.float64(np.float32(448.0) / np.float32(0.001))
+    w2, a2 = O.fp8_scales(Ws, amax, pow2=True)
+    assert list(w2) == [256.0, 1.0, 0.5, 64.0]
+    assert list(a2) == [512.0, 256.0, 1.0, 262144.0]
+    # a power of two never exceeds the plain scale and is at least half of it
+    assert np.all(w2 <= ws) and np.all(w2 > ws / 2) and np.all(a2 <= as_) and np.all(a2 > as_ / 2)
