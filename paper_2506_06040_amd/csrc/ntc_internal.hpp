@@ -8,6 +8,14 @@
 
 #include "ntc_device.hpp"
 
+// FP16 / BF16 images carry the first layer's bias in the weights (two K-slots
+// fed with the constant 1, holding the bias split into a high and a low part)
+// and the decode adds the output layer's bias inside the sigmoid; 0 keeps
+// both biases as accumulator initial values read from LDS.
+#ifndef NTC_FOLD_BIAS
+#define NTC_FOLD_BIAS 1
+#endif
+
 namespace ntc {
 
 // Shape summary of an MLP accepted by the library.
@@ -29,7 +37,9 @@ struct MlpShape {
 // inputs (FP16, 8 halves per lane) or 64 inputs (E4M3, 32 bytes per lane)),
 // then bias fragments [m][lane half][16] floats laid out like the 32x32
 // accumulator, then (FP8) three floats per layer: the input scale s_a, the
-// epilogue scale and the weight scale s_w.
+// epilogue scale and the weight scale s_w. With NTC_FOLD_BIAS, the first
+// layer's FP16 / BF16 fragments hold its bias in K-slots 6 and 7 of lane
+// half 1 (high part, then the remainder), which the decode feeds with 1.
 // ---------------------------------------------------------------------------
 struct PackLayout {
   size_t total;

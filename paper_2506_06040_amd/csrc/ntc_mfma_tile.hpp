@@ -313,6 +313,16 @@ __device__ __forceinline__ int row_max_i(int v) {
   return v;
 }
 
+// Sigmoid on the hardware exp2 / reciprocal; sigmoid_nb(z, nb) is
+// sigmoid(z + b) for nb = -log2(e) b.
+constexpr float kLog2E = 1.4426950408889634f;
+__device__ __forceinline__ float sigmoid_fast(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-kLog2E * z));
+}
+__device__ __forceinline__ float sigmoid_nb(float z, float nb) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(fmaf(z, -kLog2E, nb)));
+}
+
 // Register-resident weights of one MLP (32-row M-tiles, K-steps of the
 // precision's width).
 template <class P, int HID, int NL>
@@ -329,6 +339,10 @@ struct MfmaWeights {
   float in_scale;
   float unit_flag;  // FP16 image scaled for ReLU by clamp (1.0) or not (0.0), as loaded
   int unit_relu;    // the same, wave-uniform (set by ready())
+  // output bias of accumulator rows 4 h + i (i < 4) of this lane's half h,
+  // times -log2(e): the sigmoid's exponent is then one multiply-add
+  // (NTC_FOLD_BIAS; rows 8 + 4 h + i of widths above 8 are read where used)
+  float ob[4];
 
   __device__ __forceinline__ void load(const uint8_t *packed, const PackLayout &lay, int lane) {
     const Frag *f = reinterpret_cast<const Frag *>(packed + lay.w_off[0]);
@@ -348,6 +362,13 @@ struct MfmaWeights {
     in_scale = 1.0f;
     unit_flag = 0.0f;
     unit_relu = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ob[i] = 0.0f;
+    if (NTC_FOLD_BIAS) {
+      const float *bo = reinterpret_cast<const float *>(packed + lay.b_off[NL - 1]) + 16 * (lane >> 5);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ob[i] = -kLog2E * gload(bo + i);
+    }
 #pragma unroll
     for (int l = 0; l < kMaxLayers; ++l) epi[l] = 1.0f;
     if (P::kUnitReLU) unit_flag = gload(reinterpret_cast<const float *>(packed + lay.scale_off));
@@ -378,6 +399,8 @@ struct MfmaWeights {
     for (int l = 0; l < kMaxLayers; ++l) asm volatile("" ::"v"(epi[l]));
     asm volatile("" ::"v"(in_scale));
     asm volatile("" ::"v"(unit_flag));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) asm volatile("" ::"v"(ob[i]));
 #endif
     unit_relu = __builtin_amdgcn_readfirstlane(unit_flag != 0.0f ? 1 : 0);
     // 2^p = 0.5 * 2^(p + 1): frexp's exponent is p + 1
@@ -423,11 +446,6 @@ __device__ __forceinline__ float3 blend4(float3 t00, float3 t10, float3 t01, flo
 __device__ __forceinline__ float3 texel_direct(const uint2 *bc1, int bw, int i, int j) {
   const uint2 blk = gload2u(bc1 + (int64_t)(j >> 2) * bw + (i >> 2));
   return texel_f32(bc1_numer(blk.x, blk.y, (uint32_t)(((j & 3) << 2) | (i & 3))));
-}
-
-// Sigmoid on the hardware exp2 / reciprocal.
-__device__ __forceinline__ float sigmoid_fast(float z) {
-  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
 }
 
 // ---------------------------------------------------------------------------
@@ -477,10 +495,15 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
   const int h = (threadIdx.x & 63) >> 5;
   bias += opaque_zero(salt);
 
+  // the first layer's bias is in its weights (FP16 / BF16) and the output
+  // layer's is added by the sigmoid (NTC_FOLD_BIAS): those accumulators
+  // start at 0
+  constexpr bool kFold0 = NTC_FOLD_BIAS && !P::kScaled;
+  const f32x16 zero = {};
   f32x16 acc[NT][MT];
 #pragma unroll
   for (int m = 0; m < MT; ++m) {
-    const f32x16 bm = BL::get(bias, BL::off(0, m), h);
+    const f32x16 bm = kFold0 ? zero : BL::get(bias, BL::off(0, m), h);
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t][m] = P::mma(W.w0[m], bx[t], bm, 0, W.escale);
   }
@@ -504,7 +527,7 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
   Frag hb[NT][KS];
 #pragma unroll
   for (int t = 0; t < NT; ++t) P::template next_operands<MT, KS, UNIT>(acc[t], hb[t], W.epi[NL - 2]);
-  const f32x16 bo = BL::get(bias, BL::off_out(), h);
+  const f32x16 bo = NTC_FOLD_BIAS ? zero : BL::get(bias, BL::off_out(), h);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     f32x16 s = P::mma(W.wo[0], hb[t][0], bo, NL - 1, W.escale);
@@ -518,8 +541,8 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
 // NT - 1 of the span) and store. VEC4: the output width is a multiple of 4.
 template <class P, int NT, bool VEC4, bool IDX = false>
 __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buffer_rsrc_t ors,
-                                              const f32x16 (&z)[NT], int t0, int salt, int64_t first = 0,
-                                              int span = 0, float *obuf = nullptr) {
+                                              const f32x16 (&z)[NT], const float (&ob)[4], int t0, int salt,
+                                              int64_t first = 0, int span = 0, float *obuf = nullptr) {
   const int lane = (threadIdx.x & 63);
   const int h = lane >> 5;
   // Widths that are not a multiple of 4 store up to eight values per lane
@@ -552,13 +575,22 @@ __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buff
     for (int j = 0; j < 2; ++j) {
       if (j == 0 || two_groups) {
         f32x4 zj = {z[t][4 * j], z[t][4 * j + 1], z[t][4 * j + 2], z[t][4 * j + 3]};
-        if (j > 0) asm volatile("" : "+v"(zj));
+        f32x4 nb = {ob[0], ob[1], ob[2], ob[3]};
+        if (j > 0) {
+          asm volatile("" : "+v"(zj));
+          if (NTC_FOLD_BIAS) {
+            // rows 8 + 4 h .. + 3: elements 4 .. 7 of half h of the packed
+            // output bias fragment ([half][16] floats)
+            nb = gload(reinterpret_cast<const f32x4 *>(a.packed + a.lay.b_off[a.n_layers - 1]) + 4 * h + 1);
+            nb = nb * -kLog2E;
+          }
+        }
         // (widths that are not a multiple of 4: rows that are outputs for no
         // lane of the group are skipped; the test is wavefront-uniform)
         f32x4 f = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (VEC4 || 8 * j + i < n_out) f[i] = sigmoid_fast(zj[i]);
+          if (VEC4 || 8 * j + i < n_out) f[i] = NTC_FOLD_BIAS ? sigmoid_nb(zj[i], nb[i]) : sigmoid_fast(zj[i]);
         const int row = 8 * j + 4 * h;
         // rows past the output width and pixels past the end go beyond the
         // buffer and are dropped by its range check
@@ -636,7 +668,7 @@ __device__ __forceinline__ void mlp_store(const DecodeArgs &a, const MfmaWeights
                                           int span = 0, float *obuf = nullptr) {
   f32x16 z[NT];
   mlp_compute<P, HID, NL, NT, UNIT>(W, bias, bx, z, salt);
-  store_outputs<P, NT, VEC4, IDX>(a, ors, z, t0, salt, first, span, obuf);
+  store_outputs<P, NT, VEC4, IDX>(a, ors, z, W.ob, t0, salt, first, span, obuf);
 }
 
 
@@ -938,8 +970,9 @@ __device__ __forceinline__ void pixel_operands(float (&xl)[8], float (&xh)[8], f
                                                typename P::Frag (&bx)[2]) {
   xl[6] = uq;
   xl[7] = vq;
-  xh[6] = 0.0f;
-  xh[7] = 0.0f;
+  // FP16 / BF16 with NTC_FOLD_BIAS: the slots of the first layer's bias
+  xh[6] = (NTC_FOLD_BIAS && !P::kScaled) ? 1.0f : 0.0f;
+  xh[7] = xh[6];
   bx[0] = P::features(xl, in_scale);
   bx[1] = P::features(xh, in_scale);
   swap_halves<P>(bx[0], bx[1]);

@@ -84,8 +84,16 @@ __device__ __forceinline__ int feature_col(int n_levels, int h, int e) {
 // 32-row tile):
 //   FP16, K-step 16: element e is unit 32 (c/2) + 16 (c%2) + 8 (e/4) + 4 h + e%4
 //   E4M3, K-step 64: element e is unit 32 (2c + e/16) + 8 ((e%16)/4) + 4 h + e%4
+// With NTC_FOLD_BIAS the first layer's K-slots 6 and 7 of lane half 1 (fed
+// with 1 by the decode) take the bias: kColBiasHi, kColBiasLo.
+constexpr int kColBiasHi = -2, kColBiasLo = -3;
+
 __device__ __forceinline__ int frag_source_col(const MlpShape &s, bool f8, int l, int c, int h, int e) {
-  if (l == 0) return (f8 && e >= 8) ? -1 : feature_col((s.in_dim - 2) / 3, h, e);
+  if (l == 0) {
+    if (f8) return e >= 8 ? -1 : feature_col((s.in_dim - 2) / 3, h, e);
+    if (NTC_FOLD_BIAS && h == 1 && e >= 6) return e == 6 ? kColBiasHi : kColBiasLo;
+    return feature_col((s.in_dim - 2) / 3, h, e);
+  }
   int u;
   if (f8)
     u = 32 * (2 * c + (e >> 4)) + 8 * ((e & 15) >> 2) + 4 * h + (e & 3);
@@ -265,6 +273,21 @@ __global__ void pack_kernel(PackArgs a, int64_t n_w_elems, int64_t n_elems) {
         const int rows = a.p.dims[l + 1], cols = a.p.dims[l];
         float v = 0.f;
         if (row < rows && col >= 0 && col < cols) v = a.p.W[l][(int64_t)row * cols + col];
+        if (col <= kColBiasHi) {
+          // first-layer bias as two weights of the constant-1 slots: the
+          // operand-type value nearest the bias, then the nearest value to
+          // the remainder (exact in FP32)
+          float bv = row < rows ? a.p.b[0][row] : 0.f;
+          if (a.compute == 1) bv = ldexpf(bv, -((const int *)(a.packed + L.exp_off))[row < 64 ? row : 0]);
+          if (a.compute == 2) {
+            const __bf16 hi = (__bf16)bv;
+            ((__bf16 *)(a.packed + L.w_off[l]))[r] = col == kColBiasHi ? hi : (__bf16)(bv - (float)hi);
+          } else {
+            const _Float16 hi = (_Float16)bv;
+            ((_Float16 *)(a.packed + L.w_off[l]))[r] = col == kColBiasHi ? hi : (_Float16)(bv - (float)hi);
+          }
+          return;
+        }
         if (f8) {
           (a.packed + L.w_off[l])[r] = to_e4m3(v * sc[3 * l + 2]);
         } else if (a.compute == 2) {

@@ -430,9 +430,10 @@ def test_c2_f32_full_size(c2_case):
 # with sum|terms| / |z| of order 10 a conversion flips with probability
 # below 2 * 4e-6 * 10 / 2^-4 ~ 1.3e-3 and a pixel (206 conversions) rarely
 # sees more than one. Pixels without a flip agree to FP32 rounding; a flip
-# moves one activation by one E4M3 step, which the gate tolerates.
+# moves one activation by one E4M3 step, which the gate tolerates. Measured
+# on the C4 workload: 98.9 % of sampled pixels within 1e-4, max 5.8e-3.
 FP8_EMU_MATCH_TOL = 1e-4
-FP8_EMU_MIN_MATCH = 0.9
+FP8_EMU_MIN_MATCH = 0.95
 
 
 def test_c4_fp8_full_size(c2_case):
