@@ -304,6 +304,24 @@ ntc_status ntc_classify(const uint16_t *mat_ids, int32_t width, int32_t height, 
                         int32_t *mat_offsets, int32_t *mat_simple, uint8_t *tile_class, void *workspace,
                         size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, per-frame serving loops, harnesses that forbid allocation): the
+ * same classification as ntc_classify, with the same arguments and outputs
+ * but no workspace argument. The counts that ntc_classify keeps in its
+ * workspace live in a file-scope device array of 8 MiB, one per GPU the
+ * library runs on, held until the process ends; its device address is
+ * looked up on the first call on each device. The call allocates and frees
+ * nothing. Frames needing more than 8 MiB of counts,
+ * 8 n_mats (ceil(tiles / 128) + 1) bytes with tiles = ceil(width / 8)
+ * ceil(height / 4) (for example 4096 x 4096 with more than 255 materials),
+ * are rejected with NTC_E_WORKSPACE. Every call on one GPU shares that
+ * GPU's array: calls that overlap in time on one GPU (different streams,
+ * or threads) race and give wrong lists; calls ordered on one stream do
+ * not. */
+ntc_status ntc_classify_noalloc(const uint16_t *mat_ids, int32_t width, int32_t height, int32_t n_mats,
+                                int32_t *pixel_list, int32_t *mat_offsets, int32_t *mat_simple,
+                                uint8_t *tile_class, void *stream);
+
 /* uv[i] = uv_image[pixel_list[i]] for i < n: uv_image float [pixels][2],
  * uv float [n][2] [device, 8-byte aligned]. */
 ntc_status ntc_gather_uv(const float *uv_image, const int32_t *pixel_list, int64_t n, float *uv, void *stream);

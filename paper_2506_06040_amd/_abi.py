@@ -98,6 +98,7 @@ SIGNATURES = {
     "ntc_qat_export_bc1": (_I32, [_P, _I32, _I32, _P, _P]),
     "ntc_classify_workspace": (_I32, [_I32, _I32, _I32, ctypes.POINTER(_SZ)]),
     "ntc_classify": (_I32, [_P, _I32, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
+    "ntc_classify_noalloc": (_I32, [_P, _I32, _I32, _I32, _P, _P, _P, _P, _P]),
     "ntc_gather_uv": (_I32, [_P, _P, _I64, _P, _P]),
     "ntc_scatter_rows": (_I32, [_P, _P, _I64, _I32, _I32, _P, _P]),
     "ntc_batched_plan_size": (_I32, [ctypes.POINTER(ntc_material), _I32, ctypes.POINTER(ntc_batch_cfg),

@@ -433,6 +433,30 @@ ntc_status ntc_classify(const uint16_t *mat_ids, int32_t width, int32_t height, 
   return ok();
 }
 
+ntc_status ntc_classify_noalloc(const uint16_t *mat_ids, int32_t width, int32_t height, int32_t n_mats,
+                                int32_t *pixel_list, int32_t *mat_offsets, int32_t *mat_simple, uint8_t *tile_class,
+                                void *stream) {
+  ntc_status st = check_frame(width, height, n_mats);
+  if (st) return st;
+  if (!mat_ids || !pixel_list || !mat_offsets || !mat_simple)
+    return fail(NTC_E_NULL, "mat_ids, pixel_list, mat_offsets or mat_simple is NULL");
+  if (!aligned(mat_ids, 2) || !aligned(pixel_list, 4) || !aligned(mat_offsets, 4) || !aligned(mat_simple, 4))
+    return fail(NTC_E_ALIGN, "misaligned classification buffer");
+  const size_t need = classify_workspace_bytes(width, height, n_mats);
+  if (need > classify_scratch_bytes())
+    return fail(NTC_E_WORKSPACE,
+                "classification of %d x %d pixels with %d materials needs %zu bytes of scratch; "
+                "ntc_classify_noalloc holds %zu (use ntc_classify with a workspace)",
+                width, height, n_mats, need, classify_scratch_bytes());
+  void *ws = nullptr;
+  hipError_t e = classify_scratch(&ws);
+  if (e != hipSuccess) return hip_fail(e, "scratch address");
+  e = launch_classify(mat_ids, width, height, n_mats, pixel_list, mat_offsets, mat_simple, tile_class, ws,
+                      (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "classification launch");
+  return ok();
+}
+
 ntc_status ntc_gather_uv(const float *uv_image, const int32_t *pixel_list, int64_t n, float *uv, void *stream) {
   if (n < 0) return fail(NTC_E_SHAPE, "n < 0");
   if (n == 0) return ok();

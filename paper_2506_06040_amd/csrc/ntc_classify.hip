@@ -19,9 +19,19 @@
 // order and row-major inside a tile.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "ntc_internal.hpp"
 
 namespace ntc {
+
+// Scratch of the allocation-free entry point (ntc_classify_noalloc): the
+// per-chunk key counts and the key totals of one classification, in a
+// file-scope device array of which every GPU holds its own copy for the
+// life of the process. Every entry the passes read is written earlier in
+// the same call, so nothing needs clearing between calls.
+constexpr size_t kClassifyScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) int32_t scratch[kClassifyScratchBytes / sizeof(int32_t)];
 
 namespace {
 
@@ -260,6 +270,31 @@ hipError_t launch_classify(const uint16_t *mat, int w, int h, int n_mats, int32_
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(classify_write_kernel, dim3(a.n_chunks), dim3(64), lds, st, a);
   return hipGetLastError();
+}
+
+size_t classify_scratch_bytes() { return kClassifyScratchBytes; }
+
+// Device address of this GPU's copy of `scratch`. In host code the array's
+// name only stands in for the symbol; its device address is looked up once
+// per device (with that device current) and kept.
+hipError_t classify_scratch(void **ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_gather_uv(const float *uv_image, const int32_t *list, int64_t n, float *uv, hipStream_t st) {

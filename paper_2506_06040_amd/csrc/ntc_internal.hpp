@@ -169,6 +169,8 @@ int classify_chunks(int w, int h);
 size_t classify_workspace_bytes(int w, int h, int n_mats);
 hipError_t launch_classify(const uint16_t *mat, int w, int h, int n_mats, int32_t *list, int32_t *mat_offsets,
                            int32_t *mat_simple, uint8_t *tile_class, void *workspace, hipStream_t st);
+size_t classify_scratch_bytes();       // capacity of the allocation-free variant's scratch
+hipError_t classify_scratch(void **ptr);  // this device's scratch address
 hipError_t launch_gather_uv(const float *uv_image, const int32_t *list, int64_t n, float *uv, hipStream_t st);
 hipError_t launch_scatter_rows(const void *rows, const int32_t *list, int64_t n, int c, int elem_bytes, void *image,
                                hipStream_t st);

@@ -212,3 +212,16 @@ def test_filtered_validation(A):
     lat.data[2][1] = p
     lat.shift[0][0] = 2.0
     assert call() == A.E_SHAPE
+
+
+def test_classify_noalloc_limits(A):
+    """The allocation-free classification rejects frames whose counts exceed
+    its 8 MiB scratch, and bad arguments, before any HIP call."""
+    L = A.lib()
+    # 4096 x 4096 with 300 materials needs 600 * 4097 * 4 bytes > 8 MiB
+    assert L.ntc_classify_noalloc(0x1000, 4096, 4096, 300, 0x1000, 0x1000, 0x1000, 0, None) == A.E_WORKSPACE
+    assert b"8388608" in L.ntc_last_error()
+    assert L.ntc_classify_noalloc(None, 64, 64, 3, 0x1000, 0x1000, 0x1000, 0, None) == A.E_NULL
+    assert L.ntc_classify_noalloc(0x1001, 64, 64, 3, 0x1000, 0x1000, 0x1000, 0, None) == A.E_ALIGN
+    assert L.ntc_classify_noalloc(0x1000, 0, 64, 3, 0x1000, 0x1000, 0x1000, 0, None) == A.E_SHAPE
+    assert L.ntc_classify_noalloc(0x1000, 64, 64, 0, 0x1000, 0x1000, 0x1000, 0, None) == A.E_SHAPE
