@@ -25,7 +25,7 @@ namespace ntc {
 // 64-pixel tiles per span of the batched walk.
 constexpr int kBatchSpanTiles = NTC_SPAN_TILES;
 
-template <int HID, int NL, bool VEC4, bool IDX>
+template <int HID, int NL, int VEC4, bool IDX>
 __device__ __forceinline__ void run_material(const BatchMaterial &M, const BatchItem *items, int it0, int it1,
                                              f32x4 *stage, f32x4 *bias, f32x4 *ltab) {
   constexpr int ST = kBatchSpanTiles;
@@ -82,12 +82,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
     int run_end = it + 1;
     while (run_end < end && items[run_end].mat == m) ++run_end;
     const BatchMaterial &M = mats[m];
-    const bool vec4 = (M.a.n_out & 3) == 0;
-#define NTC_RUN(HID, NL)                                                                    \
-  (M.a.pix ? (vec4 ? run_material<HID, NL, true, true>(M, items, it, run_end, stage, bias, ltab)     \
-                   : run_material<HID, NL, false, true>(M, items, it, run_end, stage, bias, ltab))   \
-           : (vec4 ? run_material<HID, NL, true, false>(M, items, it, run_end, stage, bias, ltab)    \
-                   : run_material<HID, NL, false, false>(M, items, it, run_end, stage, bias, ltab)))
+    const int oc = out_class(M.a.n_out);
+#define NTC_RUN_O(HID, NL, IDX)                                                                        \
+  (oc == kOut4 ? run_material<HID, NL, kOut4, IDX>(M, items, it, run_end, stage, bias, ltab)            \
+               : (oc == kOut4x2 ? run_material<HID, NL, kOut4x2, IDX>(M, items, it, run_end, stage, bias, ltab) \
+                                : run_material<HID, NL, kOutAny, IDX>(M, items, it, run_end, stage, bias, ltab)))
+#define NTC_RUN(HID, NL) (M.a.pix ? NTC_RUN_O(HID, NL, true) : NTC_RUN_O(HID, NL, false))
     switch (M.shape_id) {
       case 0: NTC_RUN(16, 2); break;
       case 1: NTC_RUN(16, 3); break;
@@ -101,6 +101,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
       default: break;
     }
 #undef NTC_RUN
+#undef NTC_RUN_O
     it = run_end;
   }
 }

@@ -86,7 +86,7 @@ __device__ __forceinline__ float3 filtered_level(const FilterArgs &f, int k, flo
   return make_float3(acc.x * inv, acc.y * inv, acc.z * inv);
 }
 
-template <class P, int HID, int NL, bool VEC4, int FILTER>
+template <class P, int HID, int NL, int VEC4, int FILTER>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PER_SIMD, NTC_WAVES_PER_SIMD))) void decode_filtered_kernel(FilterArgs f) {
   extern __shared__ f32x4 smem[];
   const DecodeArgs &a = f.d;
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
   }
 }
 
-template <int HID, bool VEC4, int FILTER>
+template <int HID, int VEC4, int FILTER>
 hipError_t launch_nl(const FilterArgs &f, int n_layers, int grid, hipStream_t st) {
   const size_t lds = (size_t)BiasLds<HID, 5>::kCount * sizeof(f32x4);
   switch (n_layers) {
@@ -130,15 +130,18 @@ hipError_t launch_nl(const FilterArgs &f, int n_layers, int grid, hipStream_t st
   return hipGetLastError();
 }
 
-template <int HID, bool VEC4>
+template <int HID, int VEC4>
 hipError_t launch_filter(const FilterArgs &f, int n_layers, int grid, hipStream_t st) {
   return f.filter == 1 ? launch_nl<HID, VEC4, 1>(f, n_layers, grid, st) : launch_nl<HID, VEC4, 2>(f, n_layers, grid, st);
 }
 
 template <int HID>
 hipError_t launch_vec(const FilterArgs &f, int n_layers, int grid, hipStream_t st) {
-  return (f.d.n_out & 3) == 0 ? launch_filter<HID, true>(f, n_layers, grid, st)
-                              : launch_filter<HID, false>(f, n_layers, grid, st);
+  switch (out_class(f.d.n_out)) {
+    case kOut4: return launch_filter<HID, kOut4>(f, n_layers, grid, st);
+    case kOut4x2: return launch_filter<HID, kOut4x2>(f, n_layers, grid, st);
+    default: return launch_filter<HID, kOutAny>(f, n_layers, grid, st);
+  }
 }
 
 }  // namespace

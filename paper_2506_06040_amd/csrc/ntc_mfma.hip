@@ -19,7 +19,7 @@ namespace ntc {
 // 64-pixel tiles per span (staged together).
 constexpr int kSpanTiles = NTC_SPAN_TILES;
 
-template <class P, int HID, int NL, bool VEC4>
+template <class P, int HID, int NL, int VEC4>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PER_SIMD, NTC_WAVES_PER_SIMD))) void decode_mfma_kernel(DecodeArgs a) {
   constexpr int ST = kSpanTiles;
   constexpr int SPX = 64 * ST;
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
   }
 }
 
-template <class P, int HID, bool VEC4>
+template <class P, int HID, int VEC4>
 static hipError_t launch_mfma_v(const DecodeArgs &a, int n_layers, int grid, hipStream_t st) {
   const size_t lds =
       (size_t)(a.stage_cap + BiasLds<HID, 5>::kCount + LevelTab::kCount + (VEC4 ? 0 : 32 * 16 / 4)) * sizeof(f32x4);
@@ -74,8 +74,11 @@ static hipError_t launch_mfma_v(const DecodeArgs &a, int n_layers, int grid, hip
 
 template <class P, int HID>
 static hipError_t launch_mfma_hid(const DecodeArgs &a, int n_layers, int grid, hipStream_t st) {
-  return (a.n_out & 3) == 0 ? launch_mfma_v<P, HID, true>(a, n_layers, grid, st)
-                            : launch_mfma_v<P, HID, false>(a, n_layers, grid, st);
+  switch (out_class(a.n_out)) {
+    case kOut4: return launch_mfma_v<P, HID, kOut4>(a, n_layers, grid, st);
+    case kOut4x2: return launch_mfma_v<P, HID, kOut4x2>(a, n_layers, grid, st);
+    default: return launch_mfma_v<P, HID, kOutAny>(a, n_layers, grid, st);
+  }
 }
 
 template <class P>

@@ -65,6 +65,15 @@
 #ifndef NTC_UV_PREFETCH  // load the next span's uv during the current span
 #define NTC_UV_PREFETCH 1
 #endif
+#ifndef NTC_INTERLEAVE  // staged spans: sample sub-span q + 1 beside the MLP of sub-span q
+#define NTC_INTERLEAVE 0
+#endif
+#ifndef NTC_SCHED_VALU  // with NTC_INTERLEAVE: vector instructions placed after each matrix instruction (0: free)
+#define NTC_SCHED_VALU 0
+#endif
+#ifndef NTC_SCHED_DS  // with NTC_INTERLEAVE: LDS reads placed after each matrix instruction
+#define NTC_SCHED_DS 1
+#endif
 
 namespace ntc {
 
@@ -482,7 +491,7 @@ struct BiasLds {
 };
 
 // MLP over NT N-tiles of 32 pixels (N-tiles t0 .. t0 + NT - 1 of the span) and
-// store. VEC4: the output width is a multiple of 4.
+// store. VEC4: the output-width class (see store_outputs).
 template <class P, int HID, int NL, int NT, bool UNIT>
 __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, const f32x4 *bias,
                                             const typename P::Frag (&bx)[NT], f32x16 (&z)[NT], int salt) {
@@ -537,9 +546,16 @@ __device__ __forceinline__ void mlp_compute(const MfmaWeights<P, HID, NL> &W, co
   }
 }
 
+// Output-width classes (template argument VEC4 of the store path): widths
+// that are not a multiple of 4 (rows leave one by one or through LDS),
+// multiples of 4 up to 8 (one group of four rows per lane and no branch) and
+// multiples of 4 above 8 (a second group).
+constexpr int kOutAny = 0, kOut4 = 1, kOut4x2 = 2;
+__host__ __device__ constexpr int out_class(int n_out) { return (n_out & 3) ? kOutAny : (n_out <= 8 ? kOut4 : kOut4x2); }
+
 // Sigmoid of the output pre-activations of NT N-tiles (N-tiles t0 .. t0 +
-// NT - 1 of the span) and store. VEC4: the output width is a multiple of 4.
-template <class P, int NT, bool VEC4, bool IDX = false>
+// NT - 1 of the span) and store. VEC4: the output-width class.
+template <class P, int NT, int VEC4, bool IDX = false>
 __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buffer_rsrc_t ors,
                                               const f32x16 (&z)[NT], const float (&ob)[4], int t0, int salt,
                                               int64_t first = 0, int span = 0, float *obuf = nullptr) {
@@ -557,7 +573,7 @@ __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buff
   // more than 8 outputs (at most 16). The sigmoid of the second group reads
   // its inputs through an empty asm inside the branch, so that the compiler
   // does not evaluate its transcendentals ahead of the branch.
-  const bool two_groups = n_out > 8;
+  const bool two_groups = VEC4 == kOut4 ? false : n_out > 8;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     // FP32 rows whose width is not a multiple of 4, tile of 32 pixels
@@ -599,6 +615,19 @@ __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buff
 #pragma unroll
           for (int i = 0; i < 4; ++i)
             if (row + i < n_out) obuf[(lane & 31) * n_out + row + i] = f[i];
+        } else if (VEC4 == kOut4 && !IDX) {
+          // No branch on the output type: both stores are issued, the one
+          // of the type not requested through a resource of zero size
+          // (dropped by its range check), so that a staged span stays one
+          // basic block.
+          const int off32 = row < n_out ? (pix * n_out + row) * 4 : 0x7fffffff;
+          const __amdgpu_buffer_rsrc_t r32 = a.out_f16 ? make_rsrc(nullptr, 0) : ors;
+          const __amdgpu_buffer_rsrc_t r16 = a.out_f16 ? ors : make_rsrc(nullptr, 0);
+          const half4_t hv = __builtin_convertvector(f, half4_t);
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, f),
+                                                 r32, off32, 0, NTC_STORE_AUX);
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, hv),
+                                                r16, (int)((unsigned)off32 >> 1), 0, NTC_STORE_AUX);
         } else if (VEC4) {
           const int off = row < n_out ? off0 : 0x7fffffff;
           if (a.out_f16) {
@@ -661,7 +690,7 @@ __device__ __forceinline__ void store_outputs(const DecodeArgs &a, __amdgpu_buff
 
 // MLP over NT N-tiles of 32 pixels (N-tiles t0 .. t0 + NT - 1 of the span) and
 // store.
-template <class P, int HID, int NL, int NT, bool VEC4, bool UNIT, bool IDX = false>
+template <class P, int HID, int NL, int NT, int VEC4, bool UNIT, bool IDX = false>
 __device__ __forceinline__ void mlp_store(const DecodeArgs &a, const MfmaWeights<P, HID, NL> &W,
                                           const f32x4 *bias, __amdgpu_buffer_rsrc_t ors,
                                           const typename P::Frag (&bx)[NT], int t0, int salt, int64_t first = 0,
@@ -859,7 +888,6 @@ __device__ __forceinline__ bool stage_span(const DecodeArgs &a, const float (&u)
                                            f32x4 *stage, const f32x4 *ltab, f32x4 *srec, int salt,
                                            int (&kbw)[kMaxLevels], int (&kbase)[kMaxLevels], bool &in_unit) {
   const int lane = threadIdx.x & 63;
-  const int n_levels = a.lat.n_levels;
   in_unit = false;
   if (a.lat.address != 0) return false;
   float umin = tap_coord(u[0]), umax = umin, vmin = tap_coord(v[0]), vmax = vmin;
@@ -898,7 +926,9 @@ __device__ __forceinline__ bool stage_span(const DecodeArgs &a, const float (&u)
   const int qcol0 = qbx >> 2;
   const int qncol = ((qex + 1) >> 2) - qcol0 + 1;
   const int qnrow = qey - qby + 2;
-  const int qitems = (lane >> 2) < n_levels ? __mul24(qncol, qnrow) : 0;
+  // (levels past n_levels have a zero sampling scale: their footprint is
+  // texels 0..1 x 0..1, two items)
+  const int qitems = __mul24(qncol, qnrow);
   int kib[kMaxLevels], total = 0;
 #pragma unroll
   for (int k = 0; k < kMaxLevels; ++k) {
@@ -993,26 +1023,25 @@ __device__ __forceinline__ void staged_operands(const DecodeArgs &a, const f32x4
                                                 float uq, float vq, float in_scale, int salt,
                                                 typename P::Frag (&bx)[2]) {
   float xl[8], xh[8];
+  // every level is sampled (levels past n_levels are harmless, see
+  // to_lat_args): no branch, so a whole staged sub-span is one basic block
 #pragma unroll
   for (int k = 0; k < kMaxLevels; ++k) {
-    float3 c = make_float3(0.f, 0.f, 0.f);
-    if (k < a.lat.n_levels) {
-      TabLevel Lk;
-      Lk.read(ltab + opaque_zero(salt), k);
-      int i0, j0;
-      float fx, fy;
-      clamp_tap(tap_coord(uq), Lk.fw, Lk.cx, Lk.wm2, i0, fx);
-      clamp_tap(tap_coord(vq), Lk.fh, Lk.cy, Lk.hm2, j0, fy);
-      // taps lie inside the staged region of the level; the row offset is
-      // one multiply-add and the byte address one shift-add (the empty asm
-      // keeps the compiler from distributing the shift over the sum)
-      int r = __mul24(j0, kbw[k]) + i0;
-      asm("" : "+v"(r));
-      const f32x4 *t = stage + kbase[k] + r;
-      const f32x4 t00 = t[0], t10 = t[1], t01 = t[kbw[k]], t11 = t[kbw[k] + 1];
-      c = blend4(make_float3(t00[0], t00[1], t00[2]), make_float3(t10[0], t10[1], t10[2]),
-                 make_float3(t01[0], t01[1], t01[2]), make_float3(t11[0], t11[1], t11[2]), fx, fy);
-    }
+    TabLevel Lk;
+    Lk.read(ltab + opaque_zero(salt), k);
+    int i0, j0;
+    float fx, fy;
+    clamp_tap(tap_coord(uq), Lk.fw, Lk.cx, Lk.wm2, i0, fx);
+    clamp_tap(tap_coord(vq), Lk.fh, Lk.cy, Lk.hm2, j0, fy);
+    // taps lie inside the staged region of the level; the row offset is
+    // one multiply-add and the byte address one shift-add (the empty asm
+    // keeps the compiler from distributing the shift over the sum)
+    int r = __mul24(j0, kbw[k]) + i0;
+    asm("" : "+v"(r));
+    const f32x4 *t = stage + kbase[k] + r;
+    const f32x4 t00 = t[0], t10 = t[1], t01 = t[kbw[k]], t11 = t[kbw[k] + 1];
+    const float3 c = blend4(make_float3(t00[0], t00[1], t00[2]), make_float3(t10[0], t10[1], t10[2]),
+                            make_float3(t01[0], t01[1], t01[2]), make_float3(t11[0], t11[1], t11[2]), fx, fy);
     put_level(xl, xh, k, c);
   }
   pixel_operands<P>(xl, xh, uq, vq, in_scale, bx);
@@ -1026,28 +1055,26 @@ __device__ __forceinline__ void direct_operands(const DecodeArgs &a, const f32x4
   float xl[8], xh[8];
 #pragma unroll
   for (int k = 0; k < kMaxLevels; ++k) {
-    float3 c = make_float3(0.f, 0.f, 0.f);
-    if (k < a.lat.n_levels) {
-      TabLevel Lk;
-      Lk.read(ltab + opaque_zero(salt), k);
-      c = sample_direct_t(Lk, uq, vq, a.lat.address);
-    }
-    put_level(xl, xh, k, c);
+    TabLevel Lk;
+    Lk.read(ltab + opaque_zero(salt), k);
+    put_level(xl, xh, k, sample_direct_t(Lk, uq, vq, a.lat.address));
   }
   pixel_operands<P>(xl, xh, uq, vq, in_scale, bx);
 }
 
 // MLP and store of sub-span q of a span (two N-tiles of 32 pixels). UNIT:
 // ReLU by the [0, 1] clamp (see PrecF16::next_operands).
-template <class P, int HID, int NL, bool VEC4, bool UNIT, bool IDX = false>
+template <class P, int HID, int NL, int VEC4, bool UNIT, bool IDX = false, bool PRIO = true>
 __device__ __forceinline__ void subspan_mlp(const DecodeArgs &a, const MfmaWeights<P, HID, NL> &W, const f32x4 *bias,
                                             __amdgpu_buffer_rsrc_t ors, const typename P::Frag (&bx)[2], int q,
                                             int salt, int64_t first = 0, int span = 0, float *obuf = nullptr) {
   using Frag = typename P::Frag;
   // The other wave of the SIMD is usually sampling (vector work): issuing
   // this wave's matrix chain first lets the two overlap instead of both
-  // waves reaching the MLP together.
-  __builtin_amdgcn_s_setprio(NTC_MLP_PRIO);
+  // waves reaching the MLP together. (PRIO false: the caller interleaves
+  // its own sampling with the chain, and the priority changes would fence
+  // the scheduler.)
+  if (PRIO) __builtin_amdgcn_s_setprio(NTC_MLP_PRIO);
   // both N-tiles in one MLP pass when the weights leave room for two sets of
   // accumulators, otherwise one after the other
   if constexpr (HID >= 64 && NL >= 3 && NTC_WIDE_NT == 1) {
@@ -1057,7 +1084,7 @@ __device__ __forceinline__ void subspan_mlp(const DecodeArgs &a, const MfmaWeigh
   } else {
     mlp_store<P, HID, NL, 2, VEC4, UNIT, IDX>(a, W, bias, ors, bx, 2 * q, salt, first, span, obuf);
   }
-  __builtin_amdgcn_s_setprio(0);
+  if (PRIO) __builtin_amdgcn_s_setprio(0);
 }
 
 // Output resource of a span: stores past `span` pixels are dropped.
@@ -1072,7 +1099,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t span_out(const DecodeArgs &a, 
 // during this span, so that its latency overlaps the work of the span.
 // obuf (2 KB of LDS, or nullptr): output staging of the FP32 rows of widths
 // that are not a multiple of 4 (see store_outputs).
-template <class P, int HID, int NL, int ST, bool VEC4, bool IDX = false>
+template <class P, int HID, int NL, int ST, int VEC4, bool IDX = false>
 __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, int64_t end_px, f32x4 *stage,
                                             const f32x4 *bias, f32x4 *ltab, const MfmaWeights<P, HID, NL> &W,
                                             SpanUv<ST> &uvs, int64_t next_first, int64_t next_end_px,
@@ -1109,6 +1136,36 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     // whose stores the range check drops): that fixed count lets the wait
     // for these uv at the next span leave the stores in flight.
     if (NTC_UV_PREFETCH && next_first >= 0) uvs.template load_any<IDX>(a, next_first, next_end_px);
+    if (NTC_INTERLEAVE) {
+      // operands of sub-span q + 1 are formed in the same basic block as the
+      // matrix chain of sub-span q, which the scheduler can interleave
+      Frag bx[2];
+      staged_operands<P>(a, stage, ltab, kbw, kbase, u[0], v[0], W.in_scale, span_salt, bx);
+      NTC_UNROLL_STAGED
+      for (int q = 0; q < ST; ++q) {
+        Frag nx[2] = {bx[0], bx[1]};
+        if (q + 1 < ST)
+          staged_operands<P>(a, stage, ltab, kbw, kbase, u[q + 1], v[q + 1], W.in_scale, span_salt + q + 1, nx);
+        subspan_mlp<P, HID, NL, VEC4, P::kUnitReLU, IDX, false>(a, W, bias, ors, bx, q, span_salt + 2 * q, first,
+                                                                span, obuf);
+        bx[0] = nx[0];
+        bx[1] = nx[1];
+        if (NTC_SCHED_VALU > 0) {
+          // spread this sub-span's vector work (its epilogues and the next
+          // sub-span's sampling) over the shadows of its matrix instructions
+          constexpr int MT = (HID + 31) / 32, KS = (HID + P::KSTEP - 1) / P::KSTEP;
+          constexpr int n_mfma = 2 * (MT + (NL - 2) * MT * KS + KS);
+#pragma unroll
+          for (int i = 0; i < n_mfma; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, NTC_SCHED_VALU, 0);
+            if (NTC_SCHED_DS > 0) __builtin_amdgcn_sched_group_barrier(0x100, NTC_SCHED_DS, 0);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      return;
+    }
     NTC_UNROLL_STAGED
     for (int q = 0; q < ST; ++q) {
       Frag bx[2];
