@@ -114,9 +114,10 @@ LatArgs to_lat_args(const ntc_latents *lat) {
   for (int k = 0; k < NTC_MAX_LEVELS; ++k) {
     LevelArgs &L = a.lv[k];
     // Unused levels mirror level 0 so that every pointer stays valid, with
-    // zero sampling scale and shift: the matrix-core decode samples all
-    // four levels without a branch, and such a level always reads texels
-    // (0, 0) .. (1, 1) of level 0 into features whose weights are zero.
+    // zero sampling scale and a shift of 1/2 (position 0): the matrix-core
+    // decode samples all four levels without a branch, and such a level
+    // always reads texels (0, 0) .. (1, 1) of level 0 into features whose
+    // weights are zero.
     const bool used = k < lat->n_levels;
     const int src = used ? k : 0;
     L.w = lat->width[src];
@@ -124,8 +125,8 @@ LatArgs to_lat_args(const ntc_latents *lat) {
     L.bw = L.w / 4;
     L.fw = used ? (float)L.w : 0.0f;
     L.fh = used ? (float)L.h : 0.0f;
-    L.sx = used ? lat->shift[src][0] : 0.0f;
-    L.sy = used ? lat->shift[src][1] : 0.0f;
+    L.sx = used ? lat->shift[src][0] : 0.5f;
+    L.sy = used ? lat->shift[src][1] : 0.5f;
     if (lat->format == NTC_LATENT_BC1)
       L.bc1 = (const uint2 *)lat->data[src];
     else

@@ -32,7 +32,10 @@ __device__ __forceinline__ float3 mip_sample(const FilterArgs &f, int k, int m, 
   L.h = M.h;
   L.bw = M.bw;
   L.bc1 = M.bc1;
-  return sample_direct_t(L, tap_coord(u), tap_coord(v), 0);
+  // FP16 texels and blend, as the unfiltered FP16 decode samples a level (a
+  // footprint of one texel gives its result bit for bit)
+  const Tex16 c = sample_direct16(L, tap_coord(u), tap_coord(v), 0);
+  return make_float3((float)c.rg[0], (float)c.rg[1], (float)c.b1[0]);
 }
 
 // Trilinear sample at level of detail lod (already clamped to [0, n_mips - 1]).

@@ -38,7 +38,7 @@ struct MlpShape {
 // then bias fragments [m][lane half][16] floats laid out like the 32x32
 // accumulator, then (FP8) three floats per layer: the input scale s_a, the
 // epilogue scale and the weight scale s_w. With NTC_FOLD_BIAS, the first
-// layer's FP16 / BF16 fragments hold its bias in K-slots 6 and 7 of lane
+// layer's FP16 / BF16 fragments hold its bias in K-slots 3 and 7 of lane
 // half 1 (high part, then the remainder), which the decode feeds with 1.
 // ---------------------------------------------------------------------------
 struct PackLayout {

@@ -65,15 +65,7 @@
 #ifndef NTC_UV_PREFETCH  // load the next span's uv during the current span
 #define NTC_UV_PREFETCH 1
 #endif
-#ifndef NTC_INTERLEAVE  // staged spans: sample sub-span q + 1 beside the MLP of sub-span q
-#define NTC_INTERLEAVE 0
-#endif
-#ifndef NTC_SCHED_VALU  // with NTC_INTERLEAVE: vector instructions placed after each matrix instruction (0: free)
-#define NTC_SCHED_VALU 0
-#endif
-#ifndef NTC_SCHED_DS  // with NTC_INTERLEAVE: LDS reads placed after each matrix instruction
-#define NTC_SCHED_DS 1
-#endif
+
 
 namespace ntc {
 
@@ -126,6 +118,7 @@ struct PrecF16 {
   static constexpr int KSTEP = 16;
   static constexpr bool kScaled = false;
   static constexpr bool kUnitReLU = true;  // packed image scaled for ReLU by clamp
+  static constexpr bool kF16Tex = true;    // texels staged and blended as packed FP16
   static constexpr int kFeatDwords = 4;  // dwords of a fragment that carry features
   __device__ __forceinline__ static f32x16 mma(Frag a, Frag b, f32x16 c, int, const int (&)[2]) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
@@ -168,6 +161,7 @@ struct PrecBF16 {
   static constexpr int KSTEP = 16;
   static constexpr bool kScaled = false;
   static constexpr bool kUnitReLU = false;
+  static constexpr bool kF16Tex = false;
   static constexpr int kFeatDwords = 4;
   __device__ __forceinline__ static f32x16 mma(Frag a, Frag b, f32x16 c, int, const int (&)[2]) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -226,6 +220,7 @@ struct PrecF8 {
   static constexpr int KSTEP = 64;
   static constexpr bool kScaled = true;
   static constexpr bool kUnitReLU = false;
+  static constexpr bool kF16Tex = false;
   static constexpr int kFeatDwords = 2;
   // Format 0 = E4M3 for both operands. The weights' E8M0 block scale
   // (127 + p for 2^p) carries layer l's epilogue factor: byte l % 4 of
@@ -449,6 +444,48 @@ __device__ __forceinline__ float3 blend4(float3 t00, float3 t10, float3 t01, flo
   c.x = fmaf(w11, t11.x, fmaf(w01, t01.x, fmaf(w10, t10.x, w00 * t00.x)));
   c.y = fmaf(w11, t11.y, fmaf(w01, t01.y, fmaf(w10, t10.y, w00 * t00.y)));
   c.z = fmaf(w11, t11.z, fmaf(w01, t01.z, fmaf(w10, t10.z, w00 * t00.z)));
+  return c;
+}
+
+// A texel as packed FP16 values (r, g) and (b, 1): 8 bytes in LDS. The
+// constant 1 passes through the blend unchanged (every interpolation of two
+// equal values returns them exactly), which fills the first-layer K-slots
+// that carry the bias.
+struct Tex16 {
+  half2_t rg, b1;
+};
+__device__ __forceinline__ Tex16 tex16_of(float3 c) {
+  const f32x2 a = {c.x, c.y}, b = {c.z, 1.0f};
+  Tex16 t;
+  t.rg = __builtin_convertvector(a, half2_t);
+  t.b1 = __builtin_convertvector(b, half2_t);
+  return t;
+}
+__device__ __forceinline__ uint2 tex16_bits(Tex16 t) {
+  return make_uint2(__builtin_bit_cast(unsigned, t.rg), __builtin_bit_cast(unsigned, t.b1));
+}
+__device__ __forceinline__ Tex16 tex16_from(uint2 w) {
+  Tex16 t;
+  t.rg = __builtin_bit_cast(half2_t, w.x);
+  t.b1 = __builtin_bit_cast(half2_t, w.y);
+  return t;
+}
+
+// Bilinear blend of four FP16 texels in packed FP16 arithmetic: the top and
+// bottom pairs interpolated by fx, then those two by fy (each interpolation a
+// subtraction and a fused multiply-add per pair of channels). fx and fy are
+// rounded to FP16 first.
+__device__ __forceinline__ Tex16 lerp_tex16(Tex16 t00, Tex16 t10, Tex16 t01, Tex16 t11, float fx, float fy) {
+  const f32x2 f = {fx, fy};
+  const half2_t fh = __builtin_convertvector(f, half2_t);
+  const half2_t x = {fh[0], fh[0]}, y = {fh[1], fh[1]};
+  Tex16 top, bot, c;
+  top.rg = __builtin_elementwise_fma(x, t10.rg - t00.rg, t00.rg);
+  top.b1 = __builtin_elementwise_fma(x, t10.b1 - t00.b1, t00.b1);
+  bot.rg = __builtin_elementwise_fma(x, t11.rg - t01.rg, t01.rg);
+  bot.b1 = __builtin_elementwise_fma(x, t11.b1 - t01.b1, t01.b1);
+  c.rg = __builtin_elementwise_fma(y, bot.rg - top.rg, top.rg);
+  c.b1 = __builtin_elementwise_fma(y, bot.b1 - top.b1, top.b1);
   return c;
 }
 
@@ -752,15 +789,16 @@ struct TabLevel {
   }
 };
 
-// Sample of one level with direct block fetches; `mode` 0 clamp, 1 wrap.
-__device__ __forceinline__ float3 sample_direct_t(const TabLevel &L, float u, float v, int mode) {
+// Taps (columns i0, i1, rows j0, j1) and fractions of one level with direct
+// block fetches; `mode` 0 clamp, 1 wrap.
+__device__ __forceinline__ void direct_taps(const TabLevel &L, float u, float v, int mode, int &i0, int &i1, int &j0,
+                                            int &j1, float &fx, float &fy) {
   if (mode == 0) {
-    int i0, j0;
-    float fx, fy;
     clamp_tap(u, L.fw, L.cx, L.wm2, i0, fx);
     clamp_tap(v, L.fh, L.cy, L.hm2, j0, fy);
-    return blend4(texel_direct(L.bc1, L.bw, i0, j0), texel_direct(L.bc1, L.bw, i0 + 1, j0),
-                  texel_direct(L.bc1, L.bw, i0, j0 + 1), texel_direct(L.bc1, L.bw, i0 + 1, j0 + 1), fx, fy);
+    i1 = i0 + 1;
+    j1 = j0 + 1;
+    return;
   }
   float x = fmaf(u, L.fw, L.cx);
   float y = fmaf(v, L.fh, L.cy);
@@ -768,10 +806,31 @@ __device__ __forceinline__ float3 sample_direct_t(const TabLevel &L, float u, fl
   y = fminf(fmaxf(y, -16777216.0f), 16777216.0f);
   const float xf = floorf(x), yf = floorf(y);
   const int ix = (int)xf, iy = (int)yf;
-  const int i0 = address_coord(ix, L.w, 1), i1 = address_coord(ix + 1, L.w, 1);
-  const int j0 = address_coord(iy, L.h, 1), j1 = address_coord(iy + 1, L.h, 1);
+  i0 = address_coord(ix, L.w, 1);
+  i1 = address_coord(ix + 1, L.w, 1);
+  j0 = address_coord(iy, L.h, 1);
+  j1 = address_coord(iy + 1, L.h, 1);
+  fx = x - xf;
+  fy = y - yf;
+}
+
+// Sample of one level with direct block fetches (FP32 blend).
+__device__ __forceinline__ float3 sample_direct_t(const TabLevel &L, float u, float v, int mode) {
+  int i0, i1, j0, j1;
+  float fx, fy;
+  direct_taps(L, u, v, mode, i0, i1, j0, j1, fx, fy);
   return blend4(texel_direct(L.bc1, L.bw, i0, j0), texel_direct(L.bc1, L.bw, i1, j0),
-                texel_direct(L.bc1, L.bw, i0, j1), texel_direct(L.bc1, L.bw, i1, j1), x - xf, y - yf);
+                texel_direct(L.bc1, L.bw, i0, j1), texel_direct(L.bc1, L.bw, i1, j1), fx, fy);
+}
+
+// The same sample with FP16 texels and the packed FP16 blend (bit for bit
+// what the staged path computes from its LDS copy of the texels).
+__device__ __forceinline__ Tex16 sample_direct16(const TabLevel &L, float u, float v, int mode) {
+  int i0, i1, j0, j1;
+  float fx, fy;
+  direct_taps(L, u, v, mode, i0, i1, j0, j1, fx, fy);
+  return lerp_tex16(tex16_of(texel_direct(L.bc1, L.bw, i0, j0)), tex16_of(texel_direct(L.bc1, L.bw, i1, j0)),
+                    tex16_of(texel_direct(L.bc1, L.bw, i0, j1)), tex16_of(texel_direct(L.bc1, L.bw, i1, j1)), fx, fy);
 }
 
 // uv of the ST pixels a lane owns in a span of 64 ST pixels (pixel 64 q +
@@ -877,18 +936,23 @@ __device__ __forceinline__ void swap_halves(typename P::Frag &lo, typename P::Fr
 // span's footprint on level k is spanned by the taps of the extreme
 // coordinates, computed by 16 lanes in parallel (level, axis, min / max). If
 // the footprints fit the LDS region (stage_cap texels), every texel in them
-// is decoded once into `stage` (exact integer BC1 decode, scaled to FP32) and
+// is decoded once into `stage` (exact integer BC1 decode, scaled to FP32;
+// F16TEX: then rounded to FP16, 8 bytes per texel, see Tex16) and
 // the function returns true with kbw / kbase locating texel (i, j) of level
 // k at j kbw[k] + i + kbase[k]. `srec` is this wave's staging record area
 // (2 entries per level), `salt` a value that changes from span to span (see
 // opaque_zero). in_unit (set when the span is staged): every u and v of the
-// span lies in [0, 1] (NaN and infinities do not).
-template <int ST>
+// span lies in [0, 1] (NaN and infinities do not). interior: on every level
+// the sampling position of every pixel of the span lies in [0, n - 2] on
+// both axes, so the clamp of clamp_tap changes nothing.
+template <int ST, bool F16TEX>
 __device__ __forceinline__ bool stage_span(const DecodeArgs &a, const float (&u)[ST], const float (&v)[ST],
                                            f32x4 *stage, const f32x4 *ltab, f32x4 *srec, int salt,
-                                           int (&kbw)[kMaxLevels], int (&kbase)[kMaxLevels], bool &in_unit) {
+                                           int (&kbw)[kMaxLevels], int (&kbase)[kMaxLevels], bool &in_unit,
+                                           bool &interior) {
   const int lane = threadIdx.x & 63;
   in_unit = false;
+  interior = false;
   if (a.lat.address != 0) return false;
   float umin = tap_coord(u[0]), umax = umin, vmin = tap_coord(v[0]), vmax = vmin;
 #pragma unroll
@@ -912,6 +976,9 @@ __device__ __forceinline__ bool stage_span(const DecodeArgs &a, const float (&u)
   const f32x4 tb = (ltab + opaque_zero(salt))[3 * (le >> 1) + (le & 1)];
   const float ext = (lane & 2) ? ((lane & 1) ? vmax : vmin) : ((lane & 1) ? umax : umin);
   const int ti = (int)tap_floor(ext, tb[0], tb[1], tb[2]);
+  // the positions are monotonic in the coordinate: the extremes decide
+  const float raw = fmaf(ext, tb[0], tb[1]);
+  interior = __builtin_amdgcn_ballot_w64(lane < 16 && !(raw >= 0.0f && raw <= tb[2])) == 0;
   // every lane of quad k receives the four values of level k
   const int qbx = __builtin_amdgcn_mov_dpp(ti, 0x00, 0xF, 0xF, false);
   const int qex = __builtin_amdgcn_mov_dpp(ti, 0x55, 0xF, 0xF, false);
@@ -974,7 +1041,10 @@ __device__ __forceinline__ bool stage_span(const DecodeArgs &a, const float (&u)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const float3 val = texel_f32(bc1_numer(b.x, b.y, pos + i));
-      stage[4 * t + i] = (f32x4){val.x, val.y, val.z, 0.0f};
+      if constexpr (F16TEX)
+        reinterpret_cast<uint2 *>(stage)[4 * t + i] = tex16_bits(tex16_of(val));
+      else
+        stage[4 * t + i] = (f32x4){val.x, val.y, val.z, 0.0f};
     }
   };
   {
@@ -995,14 +1065,32 @@ __device__ __forceinline__ bool stage_span(const DecodeArgs &a, const float (&u)
 // (u, v) in the half-0 slots, levels 2, 3 in the half-1 slots), converted to
 // the operand type and exchanged between the lane halves (swap_halves): bx[0]
 // then feeds the N-tile of lanes 0..31's pixels, bx[1] that of lanes 32..63.
+// Left/top tap and fraction of a staged pixel. INTERIOR (the span's
+// positions lie in [0, n - 2]): floor and fraction of the position as they
+// stand, which is what clamp_tap gives there; otherwise clamp_tap of the
+// sanitised coordinate.
+template <bool INTERIOR>
+__device__ __forceinline__ void span_tap(float u, float f, float c, float capf, int &i0, float &fr) {
+  if (INTERIOR) {
+    const float x = fmaf(u, f, c);
+    i0 = (int)x;  // x >= 0: truncation is the floor
+    fr = __builtin_amdgcn_fractf(x);
+  } else {
+    clamp_tap(tap_coord(u), f, c, capf, i0, fr);
+  }
+}
+
+// K-slots of the first layer (element e of lane half h): half 0 holds
+// [L0 r, g, b, u, L1 r, g, b, v], half 1 [L2 r, g, b, c, L3 r, g, b, c],
+// c = 1 in the slots of the first layer's bias (FP16 / BF16 with
+// NTC_FOLD_BIAS) and 0 otherwise.
 template <class P>
 __device__ __forceinline__ void pixel_operands(float (&xl)[8], float (&xh)[8], float uq, float vq, float in_scale,
                                                typename P::Frag (&bx)[2]) {
-  xl[6] = uq;
+  xl[3] = uq;
   xl[7] = vq;
-  // FP16 / BF16 with NTC_FOLD_BIAS: the slots of the first layer's bias
-  xh[6] = (NTC_FOLD_BIAS && !P::kScaled) ? 1.0f : 0.0f;
-  xh[7] = xh[6];
+  xh[3] = (NTC_FOLD_BIAS && !P::kScaled) ? 1.0f : 0.0f;
+  xh[7] = xh[3];
   bx[0] = P::features(xl, in_scale);
   bx[1] = P::features(xh, in_scale);
   swap_halves<P>(bx[0], bx[1]);
@@ -1010,18 +1098,50 @@ __device__ __forceinline__ void pixel_operands(float (&xl)[8], float (&xh)[8], f
 
 __device__ __forceinline__ void put_level(float (&xl)[8], float (&xh)[8], int k, float3 c) {
   float *x = k < 2 ? xl : xh;
-  const int o = 3 * (k & 1);
+  const int o = 4 * (k & 1);
   x[o] = c.x;
   x[o + 1] = c.y;
   x[o + 2] = c.z;
 }
 
+// FP16 operands from FP16 level samples (same K-slots as pixel_operands):
+// each level's (r, g) and (b, 1) are fragment dwords as they stand; the pads
+// of levels 0 and 1 take u and v.
+__device__ __forceinline__ void operands16(const Tex16 (&c)[kMaxLevels], float uq, float vq, half8_t (&bx)[2]) {
+  const f32x2 uvf = {uq, vq};
+  const half2_t uv = __builtin_convertvector(uvf, half2_t);
+  const half2_t bu = {c[0].b1[0], uv[0]}, bv = {c[1].b1[0], uv[1]};
+  bx[0] = (half8_t){c[0].rg[0], c[0].rg[1], bu[0], bu[1], c[1].rg[0], c[1].rg[1], bv[0], bv[1]};
+  bx[1] = (half8_t){c[2].rg[0], c[2].rg[1], c[2].b1[0], c[2].b1[1], c[3].rg[0], c[3].rg[1], c[3].b1[0], c[3].b1[1]};
+  swap_halves<PrecF16>(bx[0], bx[1]);
+}
+
 // Operands of the pixel (uq, vq) from the staged texels.
-template <class P>
+template <class P, bool INTERIOR>
 __device__ __forceinline__ void staged_operands(const DecodeArgs &a, const f32x4 *stage, const f32x4 *ltab,
                                                 const int (&kbw)[kMaxLevels], const int (&kbase)[kMaxLevels],
                                                 float uq, float vq, float in_scale, int salt,
                                                 typename P::Frag (&bx)[2]) {
+  if constexpr (P::kF16Tex) {
+    const uint2 *s16 = reinterpret_cast<const uint2 *>(stage);
+    Tex16 c[kMaxLevels];
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k) {
+      TabLevel Lk;
+      Lk.read(ltab + opaque_zero(salt), k);
+      int i0, j0;
+      float fx, fy;
+      span_tap<INTERIOR>(uq, Lk.fw, Lk.cx, Lk.wm2, i0, fx);
+      span_tap<INTERIOR>(vq, Lk.fh, Lk.cy, Lk.hm2, j0, fy);
+      int r = __mul24(j0, kbw[k]) + i0;
+      asm("" : "+v"(r));
+      const uint2 *t = s16 + kbase[k] + r;
+      c[k] = lerp_tex16(tex16_from(t[0]), tex16_from(t[1]), tex16_from(t[kbw[k]]), tex16_from(t[kbw[k] + 1]), fx,
+                        fy);
+    }
+    operands16(c, uq, vq, bx);
+    return;
+  }
   float xl[8], xh[8];
   // every level is sampled (levels past n_levels are harmless, see
   // to_lat_args): no branch, so a whole staged sub-span is one basic block
@@ -1031,8 +1151,8 @@ __device__ __forceinline__ void staged_operands(const DecodeArgs &a, const f32x4
     Lk.read(ltab + opaque_zero(salt), k);
     int i0, j0;
     float fx, fy;
-    clamp_tap(tap_coord(uq), Lk.fw, Lk.cx, Lk.wm2, i0, fx);
-    clamp_tap(tap_coord(vq), Lk.fh, Lk.cy, Lk.hm2, j0, fy);
+    span_tap<INTERIOR>(uq, Lk.fw, Lk.cx, Lk.wm2, i0, fx);
+    span_tap<INTERIOR>(vq, Lk.fh, Lk.cy, Lk.hm2, j0, fy);
     // taps lie inside the staged region of the level; the row offset is
     // one multiply-add and the byte address one shift-add (the empty asm
     // keeps the compiler from distributing the shift over the sum)
@@ -1052,6 +1172,17 @@ __device__ __forceinline__ void staged_operands(const DecodeArgs &a, const f32x4
 template <class P>
 __device__ __forceinline__ void direct_operands(const DecodeArgs &a, const f32x4 *ltab, float uq, float vq,
                                                 float in_scale, int salt, typename P::Frag (&bx)[2]) {
+  if constexpr (P::kF16Tex) {
+    Tex16 c[kMaxLevels];
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k) {
+      TabLevel Lk;
+      Lk.read(ltab + opaque_zero(salt), k);
+      c[k] = sample_direct16(Lk, uq, vq, a.lat.address);
+    }
+    operands16(c, uq, vq, bx);
+    return;
+  }
   float xl[8], xh[8];
 #pragma unroll
   for (int k = 0; k < kMaxLevels; ++k) {
@@ -1120,9 +1251,9 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     v[q] = uvs.v[q];
   }
   int kbw[kMaxLevels], kbase[kMaxLevels];
-  bool in_unit;
-  const bool staged =
-      stage_span<ST>(a, u, v, stage, ltab, ltab + LevelTab::kLevelEntries, span_salt, kbw, kbase, in_unit);
+  bool in_unit, interior;
+  const bool staged = stage_span<ST, P::kF16Tex>(a, u, v, stage, ltab, ltab + LevelTab::kLevelEntries, span_salt,
+                                                 kbw, kbase, in_unit, interior);
 
   // FP16: the staged path runs with ReLU by clamp, so it takes only spans
   // whose activations are known to be at most 1 (image scaled for it,
@@ -1136,41 +1267,24 @@ __device__ __forceinline__ void decode_span(const DecodeArgs &a, int64_t first, 
     // whose stores the range check drops): that fixed count lets the wait
     // for these uv at the next span leave the stores in flight.
     if (NTC_UV_PREFETCH && next_first >= 0) uvs.template load_any<IDX>(a, next_first, next_end_px);
-    if (NTC_INTERLEAVE) {
-      // operands of sub-span q + 1 are formed in the same basic block as the
-      // matrix chain of sub-span q, which the scheduler can interleave
-      Frag bx[2];
-      staged_operands<P>(a, stage, ltab, kbw, kbase, u[0], v[0], W.in_scale, span_salt, bx);
+    // spans whose taps lie inside every level: no clamp on the tap
+    // coordinates (same result, fewer instructions)
+    if (interior) {
       NTC_UNROLL_STAGED
       for (int q = 0; q < ST; ++q) {
-        Frag nx[2] = {bx[0], bx[1]};
-        if (q + 1 < ST)
-          staged_operands<P>(a, stage, ltab, kbw, kbase, u[q + 1], v[q + 1], W.in_scale, span_salt + q + 1, nx);
-        subspan_mlp<P, HID, NL, VEC4, P::kUnitReLU, IDX, false>(a, W, bias, ors, bx, q, span_salt + 2 * q, first,
-                                                                span, obuf);
-        bx[0] = nx[0];
-        bx[1] = nx[1];
-        if (NTC_SCHED_VALU > 0) {
-          // spread this sub-span's vector work (its epilogues and the next
-          // sub-span's sampling) over the shadows of its matrix instructions
-          constexpr int MT = (HID + 31) / 32, KS = (HID + P::KSTEP - 1) / P::KSTEP;
-          constexpr int n_mfma = 2 * (MT + (NL - 2) * MT * KS + KS);
-#pragma unroll
-          for (int i = 0; i < n_mfma; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x002, NTC_SCHED_VALU, 0);
-            if (NTC_SCHED_DS > 0) __builtin_amdgcn_sched_group_barrier(0x100, NTC_SCHED_DS, 0);
-          }
-          __builtin_amdgcn_sched_barrier(0);
-        }
+        Frag bx[2];
+        staged_operands<P, true>(a, stage, ltab, kbw, kbase, u[q], v[q], W.in_scale, span_salt + q, bx);
+        subspan_mlp<P, HID, NL, VEC4, P::kUnitReLU, IDX>(a, W, bias, ors, bx, q, span_salt + 2 * q, first, span,
+                                                         obuf);
       }
-      return;
-    }
-    NTC_UNROLL_STAGED
-    for (int q = 0; q < ST; ++q) {
-      Frag bx[2];
-      staged_operands<P>(a, stage, ltab, kbw, kbase, u[q], v[q], W.in_scale, span_salt + q, bx);
-      subspan_mlp<P, HID, NL, VEC4, P::kUnitReLU, IDX>(a, W, bias, ors, bx, q, span_salt + 2 * q, first, span, obuf);
+    } else {
+      NTC_UNROLL_STAGED
+      for (int q = 0; q < ST; ++q) {
+        Frag bx[2];
+        staged_operands<P, false>(a, stage, ltab, kbw, kbase, u[q], v[q], W.in_scale, span_salt + q, bx);
+        subspan_mlp<P, HID, NL, VEC4, P::kUnitReLU, IDX>(a, W, bias, ors, bx, q, span_salt + 2 * q, first, span,
+                                                         obuf);
+      }
     }
     return;
   }

@@ -67,14 +67,16 @@ struct PackArgs {
 };
 
 // Input index fed to K-slot (lane half h, element e) of the first layer:
-// half 0 carries levels 0 and 1 and (u, v), half 1 levels 2 and 3.
+// half 0 carries [L0 r, g, b, u, L1 r, g, b, v], half 1 [L2 r, g, b, -,
+// L3 r, g, b, -] (a level's three channels and one more slot per group of
+// four, so that a level's packed FP16 sample (r, g), (b, x) is two operand
+// dwords as it stands).
 __device__ __forceinline__ int feature_col(int n_levels, int h, int e) {
-  if (e < 6) {
-    const int lvl = 2 * h + (e >= 3 ? 1 : 0);
-    return lvl < n_levels ? 3 * lvl + (e >= 3 ? e - 3 : e) : -1;
+  if ((e & 3) < 3) {
+    const int lvl = 2 * h + (e >> 2);
+    return lvl < n_levels ? 3 * lvl + (e & 3) : -1;
   }
-  if (h == 0 && e == 6) return 3 * n_levels;
-  if (h == 0 && e == 7) return 3 * n_levels + 1;
+  if (h == 0) return 3 * n_levels + (e >> 2);  // u, v
   return -1;
 }
 
@@ -84,14 +86,14 @@ __device__ __forceinline__ int feature_col(int n_levels, int h, int e) {
 // 32-row tile):
 //   FP16, K-step 16: element e is unit 32 (c/2) + 16 (c%2) + 8 (e/4) + 4 h + e%4
 //   E4M3, K-step 64: element e is unit 32 (2c + e/16) + 8 ((e%16)/4) + 4 h + e%4
-// With NTC_FOLD_BIAS the first layer's K-slots 6 and 7 of lane half 1 (fed
+// With NTC_FOLD_BIAS the first layer's K-slots 3 and 7 of lane half 1 (fed
 // with 1 by the decode) take the bias: kColBiasHi, kColBiasLo.
 constexpr int kColBiasHi = -2, kColBiasLo = -3;
 
 __device__ __forceinline__ int frag_source_col(const MlpShape &s, bool f8, int l, int c, int h, int e) {
   if (l == 0) {
     if (f8) return e >= 8 ? -1 : feature_col((s.in_dim - 2) / 3, h, e);
-    if (NTC_FOLD_BIAS && h == 1 && e >= 6) return e == 6 ? kColBiasHi : kColBiasLo;
+    if (NTC_FOLD_BIAS && h == 1 && (e & 3) == 3) return e == 3 ? kColBiasHi : kColBiasLo;
     return feature_col((s.in_dim - 2) / 3, h, e);
   }
   int u;
