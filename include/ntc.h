@@ -184,10 +184,13 @@ ntc_status ntc_decode_backward_workspace(const ntc_latents *lat, const ntc_mlp *
  *   grad_W[l] float [dims[l+1]][dims[l]], grad_b[l] float [dims[l+1]],
  *   grad_latents[k] float [height[k]][width[k]][3]          [all device]
  * (arrays of n_layers / n_levels device pointers [host]). Activations are
- * recomputed per tile. Weight gradients are summed per workgroup in FP32 and
- * across workgroups in FP64; latent gradients are accumulated with FP32
- * atomics (their summation order is not deterministic). workspace [device,
- * 256-byte aligned] of at least ntc_decode_backward_workspace bytes. */
+ * recomputed per tile of 32 samples with FP32 matrix-core products. Weight
+ * gradients are summed per wavefront in FP32 and across wavefronts in FP64
+ * (the same inputs give the same bits); latent gradients are accumulated
+ * per spatial bin of samples in LDS and then with FP32 atomics (their
+ * summation order is not deterministic). workspace [device, 256-byte
+ * aligned] of at least ntc_decode_backward_workspace bytes (it grows with
+ * n: 4 (3 n_levels + 1) bytes per sample plus the partial sums). */
 ntc_status ntc_decode_backward(const ntc_latents *lat, const ntc_mlp *mlp, const float *uv, int64_t n,
                                const float *grad_out, float *const *grad_W, float *const *grad_b,
                                float *const *grad_latents, void *workspace, size_t ws_bytes,

@@ -23,16 +23,20 @@ FLAGS = [
     "-I" + INCLUDE,
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # matrix-core results in arch VGPRs: the epilogues read them directly
-    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall",
     "-Wno-unused-function",
     "-Wno-unused-variable",
 ]
 
 
+# Matrix-core results in arch VGPRs, where the decode epilogues read them
+# directly; the backward (one wavefront per SIMD, 512 registers) keeps its
+# gradient accumulators in the accumulation registers instead.
+PER_FILE = {s: ["-mllvm", "-amdgpu-mfma-vgpr-form=1"] for s in SOURCES if s != "ntc_backward.hip"}
+
+
 def _compile(src: str, obj: str, extra, verbose: bool) -> None:
-    cmd = [HIPCC] + FLAGS + list(extra or []) + ["-c", "-o", obj, src]
+    cmd = [HIPCC] + FLAGS + PER_FILE.get(os.path.basename(src), []) + list(extra or []) + ["-c", "-o", obj, src]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

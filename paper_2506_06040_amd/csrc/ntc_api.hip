@@ -493,8 +493,8 @@ ntc_status ntc_decode_backward_workspace(const ntc_latents *lat, const ntc_mlp *
   MlpShape s;
   if ((st = check_mlp_shape(mlp, lat->n_levels, &s))) return st;
   if (s.n_layers > 4) return fail(NTC_E_UNSUPPORTED, "backward supports at most 4 layers");
-  if (n < 0) return fail(NTC_E_SHAPE, "n < 0");
-  *bytes = backward_workspace_bytes(s, backward_blocks(n));
+  if (n < 0 || n > ((int64_t)1 << 36)) return fail(NTC_E_SHAPE, "n = %lld out of range", (long long)n);
+  *bytes = backward_layout(s, to_lat_args(lat), n).total;
   return ok();
 }
 
@@ -517,8 +517,9 @@ ntc_status ntc_decode_backward(const ntc_latents *lat, const ntc_mlp *mlp, const
     if (!grad_latents[k]) return fail(NTC_E_NULL, "latent gradient %d is NULL", k);
     if (!aligned(grad_latents[k], 4)) return fail(NTC_E_ALIGN, "latent gradient %d misaligned", k);
   }
-  const int n_blocks = backward_blocks(n);
-  const size_t need = backward_workspace_bytes(s, n_blocks);
+  const LatArgs la = to_lat_args(lat);
+  const BwdLayout lay = backward_layout(s, la, n);
+  const size_t need = lay.total;
   if (!workspace) return fail(NTC_E_NULL, "workspace is NULL");
   if (ws_bytes < need) return fail(NTC_E_WORKSPACE, "workspace needs %zu bytes, got %zu", need, ws_bytes);
   if (!aligned(workspace, 256)) return fail(NTC_E_ALIGN, "workspace must be 256-byte aligned");
@@ -541,7 +542,7 @@ ntc_status ntc_decode_backward(const ntc_latents *lat, const ntc_mlp *mlp, const
   }
   BackwardArgs a;
   memset(&a, 0, sizeof a);
-  a.lat = to_lat_args(lat);
+  a.lat = la;
   for (int l = 0; l < s.n_layers; ++l) {
     a.W[l] = mlp->W[l];
     a.b[l] = mlp->b[l];
@@ -551,10 +552,21 @@ ntc_status ntc_decode_backward(const ntc_latents *lat, const ntc_mlp *mlp, const
   a.uv = (const float2 *)uv;
   a.grad_out = grad_out;
   for (int k = 0; k < lat->n_levels; ++k) a.grad_lat[k] = grad_latents[k];
-  a.wpart = (float *)workspace;
+  uint8_t *ws = (uint8_t *)workspace;
+  a.wpart = (float *)(ws + lay.wpart_off);
+  a.dx = (float *)(ws + lay.dx_off);
+  a.bin_count = (int32_t *)(ws + lay.count_off);
+  a.bin_cursor = (int32_t *)(ws + lay.cursor_off);
+  a.perm = (int32_t *)(ws + lay.perm_off);
   a.n = n;
-  a.n_params = backward_n_params(s);
-  a.n_blocks = n_blocks;
+  a.n_params = lay.n_params;
+  a.n_blocks = lay.n_blocks;
+  a.n_feat = lay.n_feat;
+  a.bin_tex = lay.bin_tex;
+  a.bins_x = lay.bins_x;
+  a.bins_y = lay.bins_y;
+  a.n_bins = lay.n_bins;
+  a.bin_lds = lay.bin_lds;
   hipError_t e = launch_backward(a, s, grad_W, grad_b, hs);
   if (e != hipSuccess) return hip_fail(e, "backward launch");
   return ok();

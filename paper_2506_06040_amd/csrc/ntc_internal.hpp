@@ -90,7 +90,19 @@ int decode_span_tiles();  // 64-pixel tiles per span of the matrix-core decode
 hipError_t launch_bc1_texels(const LevelArgs &L, float *out, uint16_t *numer, hipStream_t st);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
 
-// Backward.
+// Backward. Workspace (256-byte aligned sections): per-block FP32 partial
+// sums of the weight gradients, the feature gradient dL/dx of every sample,
+// and for clamp addressing the spatial bins of the latent-gradient scatter
+// (per-bin counts, then start offsets; running cursors; sample indices
+// grouped by bin).
+struct BwdLayout {
+  int32_t n_blocks, n_params, n_feat;
+  int32_t bin_tex, bins_x, bins_y, n_bins;  // n_bins = 0: no binning (wrap addressing)
+  int32_t bin_lds;                          // LDS floats of one bin's texel windows
+  size_t wpart_off, dx_off, count_off, cursor_off, perm_off, total;
+};
+BwdLayout backward_layout(const MlpShape &s, const LatArgs &lat, int64_t n);
+
 struct BackwardArgs {
   LatArgs lat;
   const float *W[kMaxLayers];
@@ -99,15 +111,18 @@ struct BackwardArgs {
   const float *grad_out;
   float *grad_lat[kMaxLevels];
   float *wpart;          // [n_blocks][n_params] FP32 per-block partial sums
+  float *dx;             // [n][n_feat] dL/d(feature) of every sample
+  int32_t *bin_count;    // [n_bins]
+  int32_t *bin_cursor;   // [n_bins]
+  int32_t *perm;         // [n]
   int64_t n;
   int32_t n_params;
   int32_t n_blocks;
+  int32_t n_feat;
+  int32_t bin_tex, bins_x, bins_y, n_bins, bin_lds;
   int32_t dims[kMaxLayers + 1];
   int32_t n_layers;
 };
-size_t backward_workspace_bytes(const MlpShape &s, int n_blocks);
-int backward_blocks(int64_t n);
-int backward_n_params(const MlpShape &s);
 hipError_t launch_backward(const BackwardArgs &a, const MlpShape &s, float *const *grad_W,
                            float *const *grad_b, hipStream_t st);
 
