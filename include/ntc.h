@@ -142,11 +142,15 @@ ntc_status ntc_mlp_pack_size(const ntc_mlp *mlp, int32_t compute, size_t *bytes)
  * weight would exceed 2^15 (FP16 holds at most 65504), the image is left
  * unscaled and every span uses the max-based ReLU.
  * For NTC_FP8_E4M3, per-layer scales are powers of two computed on the
- * device: s_w = 2^floor(log2(448 / max|W_l|)) and
- * s_a = 2^floor(log2(448 / act_amax[l])), so that scaled values stay within
- * E4M3's +-448 and the factor that maps a layer's accumulator to the next
- * layer's scaled input is itself a power of two (the decode applies it as
- * the matrix instruction's E8M0 block scale). act_amax [device, n_layers
+ * device: s_w = 2^floor(log2(448 / max|W_l|)); for the first layer's inputs
+ * s_a = 2^floor(log2(448 / max(act_amax[0], 1))) (latent values reach 1),
+ * the coordinates saturating at 448 / s_a; for hidden activations
+ * s_a = 2^floor(log2(256 / act_amax[l])), their scaled values clamped to
+ * [0, 256] (ReLU and clamp in one FP16 conversion, then a scaled FP16 ->
+ * E4M3 conversion). Scaled values thus stay within E4M3's +-448, and the
+ * factor that maps a layer's accumulator to the next layer's scaled input
+ * / 256 is itself a power of two (the decode applies it as the matrix
+ * instruction's E8M0 block scale). act_amax [device, n_layers
  * floats] must hold the largest |input| of every layer (see
  * ntc_calibrate_fp8). Otherwise act_amax is ignored. packed [device,
  * 256-byte aligned]. */

@@ -32,7 +32,7 @@ MAX_LEVELS = 8
 MAX_LAYERS = 8
 
 CLAMP, WRAP = 0, 1
-EXACT, FP16, FP8 = 0, 1, 2
+EXACT, FP16, FP8, FP8_F16 = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
@@ -120,8 +120,10 @@ class Latents:
 
 class Mlp:
     """MLP for the oracle: W[l] [dims[l+1]][dims[l]], b[l] [dims[l+1]] (any float dtype,
-    widened to float64). precision: EXACT, FP16 (round inputs and weights to binary16)
-    or FP8 (scale and round to E4M3; needs w_scale and a_scale)."""
+    widened to float64). precision: EXACT, FP16 (round inputs and weights to binary16),
+    FP8 (scale and round to E4M3; needs w_scale and a_scale) or FP8_F16 (as FP8, but
+    the scaled hidden activations are clamped to [0, 256] and reach E4M3 through
+    binary16: 256 * round_f16(min(a s / 256, 1)), then E4M3)."""
 
     def __init__(self, Ws, bs, precision: int = EXACT, w_scale=None, a_scale=None):
         self.W = [np.ascontiguousarray(w, dtype=np.float64) for w in Ws]
@@ -142,7 +144,7 @@ class Mlp:
             self.c.b[l] = self.b[l].ctypes.data
         self.c.precision = precision
         self._ws = self._as = None
-        if precision == FP8:
+        if precision in (FP8, FP8_F16):
             self._ws = np.ascontiguousarray(w_scale, dtype=np.float64)
             self._as = np.ascontiguousarray(a_scale, dtype=np.float64)
             assert self._ws.shape == (L,) and self._as.shape == (L,)
@@ -227,13 +229,21 @@ def layer_amax(lat: Latents, mlp: Mlp, uv: np.ndarray) -> np.ndarray:
 
 def fp8_scales(Ws, amax_act, pow2: bool = False):
     """Per-layer E4M3 scales: s = 448 / max|.| computed in float32, as float64
-    values; with pow2, the largest power of two not above that quotient."""
+    values. With pow2, the power-of-two form the matrix-core path stores:
+    weights 2^floor(log2(448 / max|W_l|)); first-layer inputs
+    2^floor(log2(448 / max(amax_0, 1))) (BC1 latent values reach 1 whatever
+    the calibration saw); hidden activations 2^floor(log2(256 / amax_l)),
+    whose scaled values are clamped to [0, 256] (precision FP8_F16)."""
+    if pow2:
+        def p2(x):
+            return float(np.ldexp(1.0, np.frexp(np.float64(x))[1] - 1))
+        w_scale = np.array([p2(448.0 / np.max(np.abs(np.asarray(w, np.float32)))) for w in Ws], dtype=np.float64)
+        a_scale = np.array([p2(448.0 / max(float(a), 1.0)) if l == 0 else (p2(256.0 / float(a)) if a > 0 else 1.0)
+                            for l, a in enumerate(amax_act)], dtype=np.float64)
+        return w_scale, a_scale
     w_scale = np.array([np.float32(448.0) / np.float32(np.max(np.abs(np.asarray(w, np.float32))))
                         for w in Ws], dtype=np.float64)
     a_scale = np.array([np.float32(448.0) / np.float32(a) for a in amax_act], dtype=np.float64)
-    if pow2:
-        w_scale = np.ldexp(1.0, np.frexp(w_scale)[1] - 1)
-        a_scale = np.ldexp(1.0, np.frexp(a_scale)[1] - 1)
     return w_scale, a_scale
 
 

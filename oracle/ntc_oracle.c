@@ -51,9 +51,10 @@ typedef struct {
     int32_t dims[OR_MAX_LAYERS + 1];
     const double *W[OR_MAX_LAYERS]; /* [dims[l+1]][dims[l]] row-major */
     const double *b[OR_MAX_LAYERS];
-    int32_t precision;              /* 0 exact, 1 round to binary16, 2 round to E4M3 with scales */
-    const double *w_scale;          /* [n_layers], precision 2 only */
-    const double *a_scale;          /* [n_layers], precision 2 only */
+    int32_t precision;              /* 0 exact, 1 round to binary16, 2 round to E4M3 with scales,
+                                       3 as 2 with hidden activations through binary16 */
+    const double *w_scale;          /* [n_layers], precision 2 and 3 only */
+    const double *a_scale;          /* [n_layers], precision 2 and 3 only */
 } oracle_mlp;
 
 /* ------------------------------------------------------------------------
@@ -219,23 +220,34 @@ void oracle_features(const oracle_level *lv, int32_t n_levels, int32_t mode,
     for (int64_t s = 0; s < n; ++s) features_one(lv, n_levels, mode, uv[2 * s], uv[2 * s + 1], x + s * nf);
 }
 
+/* Quantised input of layer l. Precision 3 takes the activations of the
+ * hidden layers (l > 0, non-negative after ReLU) to E4M3 in two steps: the
+ * scaled value divided by 256 is clamped to [0, 1] and rounded to binary16,
+ * and that value times 256 (at most 256, so no saturation) is rounded to
+ * E4M3; the first layer's inputs are rounded as in precision 2. */
 static double quant_act(const oracle_mlp *m, int l, double a) {
     if (m->precision == 1) return oracle_round_f16(a);
-    if (m->precision == 2) return oracle_round_e4m3_sat(a * m->a_scale[l]);
+    if (m->precision == 3 && l > 0) {
+        double t = a * m->a_scale[l] / 256.0;
+        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+        return oracle_round_e4m3_sat(256.0 * oracle_round_f16(t));
+    }
+    if (m->precision >= 2) return oracle_round_e4m3_sat(a * m->a_scale[l]);
     return a;
 }
 
 static double quant_w(const oracle_mlp *m, int l, double w) {
     if (m->precision == 1) return oracle_round_f16(w);
-    if (m->precision == 2) return oracle_round_e4m3_sat(w * m->w_scale[l]);
+    if (m->precision >= 2) return oracle_round_e4m3_sat(w * m->w_scale[l]);
     return w;
 }
 
 /* MLP f(x) (Sec. 3.1): hidden layers h = max(0, W h + b), output layer
  * f = 1 / (1 + exp(-(W h + b))). With precision 1 the layer inputs and the
- * weights are first rounded to binary16; with precision 2 they are scaled
- * and rounded to E4M3 and the dot product is divided by both scales. The
- * bias and the accumulation stay exact in both cases. If z is not NULL the
+ * weights are first rounded to binary16; with precision 2 and 3 they are
+ * scaled and rounded to E4M3 (quant_act, quant_w) and the dot product is
+ * divided by both scales. The bias and the accumulation stay exact in every
+ * case. If z is not NULL the
  * pre-activations of every layer are stored there, layer after layer. */
 static void mlp_one(const oracle_mlp *m, const double *x, double *f, double *z_all,
                     double *amax) {
@@ -254,7 +266,7 @@ static void mlp_one(const oracle_mlp *m, const double *x, double *f, double *z_a
             double acc = 0.0;
             const double *wr = m->W[l] + (int64_t)o * di;
             for (int k = 0; k < di; ++k) acc += quant_w(m, l, wr[k]) * hq[k];
-            if (m->precision == 2) acc /= (m->w_scale[l] * m->a_scale[l]);
+            if (m->precision >= 2) acc /= (m->w_scale[l] * m->a_scale[l]);
             acc += m->b[l][o];
             if (z_all) z_all[zoff + o] = acc;
             hn[o] = (l + 1 < m->n_layers) ? (acc > 0.0 ? acc : 0.0) : 1.0 / (1.0 + exp(-acc));

@@ -195,22 +195,34 @@ struct PrecBF16 {
   }
 };
 
-// OCP E4M3 with saturation to +-448 (the conversion instruction is applied
-// to clamped values).
-__device__ __forceinline__ float sat448(float v) { return __builtin_amdgcn_fmed3f(v, -448.0f, 448.0f); }
-__device__ __forceinline__ int pack4_e4m3(float a, float b, float c, float d) {
-  int w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(a), sat448(b), 0, false);
-  return __builtin_amdgcn_cvt_pk_fp8_f32(sat448(c), sat448(d), w, true);
+// Four values to E4M3 bytes (first value in byte 0): the scaled conversion
+// gives E4M3(x / inv), inv a power of two, so the scaling is exact. It does
+// not saturate (a result beyond 448 becomes NaN): callers keep x / inv in
+// [-448, 448].
+typedef short short2_t __attribute__((ext_vector_type(2)));
+// The conversions write one half of their destination and keep the other;
+// the first of a pair writes the low half of a register whose high half the
+// second overwrites, so its kept half is left unspecified (no zeroing move).
+__device__ __forceinline__ short2_t any_short2() {
+  short2_t z;  // unset on purpose
+  return z;
+}
+__device__ __forceinline__ int pack4_e4m3(float a, float b, float c, float d, float inv) {
+  const short2_t lo = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(any_short2(), a, b, inv, false);
+  const short2_t w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(lo, c, d, inv, true);
+  return __builtin_bit_cast(int, w);
 }
 
-// ReLU of scaled values (s > 0, so max(v, 0) s = max(v s, 0)) and E4M3
-// saturation in one median: med3(v s, 0, 448).
+// Hidden activations to E4M3: the accumulators hold the next layer's scaled
+// input / 256, so ReLU and the upper clamp are the [0, 1] clamp of the FP16
+// conversion (one instruction per pair), and the scaled FP16 -> E4M3
+// conversion multiplies by 256 (values in [0, 256], never beyond E4M3's
+// range): one instruction per activation in all.
 __device__ __forceinline__ int pack4_relu_e4m3(float a, float b, float c, float d) {
-  const float lo = 0.0f, hi = 448.0f;
-  int w = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_fmed3f(a, lo, hi), __builtin_amdgcn_fmed3f(b, lo, hi), 0,
-                                          false);
-  return __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_fmed3f(c, lo, hi), __builtin_amdgcn_fmed3f(d, lo, hi), w,
-                                         true);
+  const float inv256 = 0x1p-8f;
+  const short2_t lo = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(any_short2(), relu_unit_pk(a, b), inv256, false);
+  const short2_t w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(lo, relu_unit_pk(c, d), inv256, true);
+  return __builtin_bit_cast(int, w);
 }
 
 // E4M3 operands, 32x32x64 tiles (full-rate scaled form with unit block
@@ -236,17 +248,19 @@ struct PrecF8 {
       default: return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, sc[1], 1, sc[1]);
     }
   }
-  __device__ __forceinline__ static Frag features(const float (&x)[8], float s) {
+  // inv: the reciprocal of the first layer's input scale (features times
+  // the scale stay within E4M3's range: see pixel_operands)
+  __device__ __forceinline__ static Frag features(const float (&x)[8], float inv) {
     Frag f = {0, 0, 0, 0, 0, 0, 0, 0};
-    f[0] = pack4_e4m3(x[0] * s, x[1] * s, x[2] * s, x[3] * s);
-    f[1] = pack4_e4m3(x[4] * s, x[5] * s, x[6] * s, x[7] * s);
+    f[0] = pack4_e4m3(x[0], x[1], x[2], x[3], inv);
+    f[1] = pack4_e4m3(x[4], x[5], x[6], x[7], inv);
     return f;
   }
   // K-step c of the next layer: bytes 0..15 from all rows of M-tile 2c,
   // bytes 16..31 from M-tile 2c + 1 (zero when it does not exist). The
-  // accumulators are already in the next layer's input scale (the layer's
-  // matrix instructions applied it), so this is ReLU, saturation and the
-  // conversion.
+  // accumulators are already in the next layer's input scale / 256 (the
+  // layer's matrix instructions applied it), so this is ReLU, clamp and the
+  // conversion (pack4_relu_e4m3).
   template <int MT, int KS, bool>
   __device__ __forceinline__ static void next_operands(const f32x16 (&acc)[MT], Frag (&hb)[KS], float) {
 #pragma unroll
@@ -340,7 +354,7 @@ struct MfmaWeights {
   Frag wo[KS];
   float epi[kMaxLayers];  // E4M3: epilogue factor of each layer (a power of two), as loaded
   int escale[2];          // the same as E8M0 bytes (see PrecF8::mma; set by ready())
-  float in_scale;
+  float in_scale;   // E4M3: reciprocal of the first layer's input scale
   float unit_flag;  // FP16 image scaled for ReLU by clamp (1.0) or not (0.0), as loaded
   int unit_relu;    // the same, wave-uniform (set by ready())
   // output bias of accumulator rows 4 h + i (i < 4) of this lane's half h,
@@ -378,7 +392,7 @@ struct MfmaWeights {
     if (P::kUnitReLU) unit_flag = gload(reinterpret_cast<const float *>(packed + lay.scale_off));
     if (P::kScaled) {
       const float *sc = reinterpret_cast<const float *>(packed + lay.scale_off);
-      in_scale = gload(sc);
+      in_scale = 1.0f / gload(sc);  // a power of two: exact
 #pragma unroll
       for (int l = 0; l < NL; ++l) epi[l] = gload(sc + 3 * l + 1);
     }
@@ -1087,6 +1101,13 @@ __device__ __forceinline__ void span_tap(float u, float f, float c, float capf, 
 template <class P>
 __device__ __forceinline__ void pixel_operands(float (&xl)[8], float (&xh)[8], float uq, float vq, float in_scale,
                                                typename P::Frag (&bx)[2]) {
+  if constexpr (P::kScaled) {
+    // E4M3: the coordinates saturate at the largest finite value (the
+    // latents, at most 1, fit: their scale is at most 256)
+    const float lim = 448.0f * in_scale;
+    uq = __builtin_amdgcn_fmed3f(uq, -lim, lim);
+    vq = __builtin_amdgcn_fmed3f(vq, -lim, lim);
+  }
   xl[3] = uq;
   xl[7] = vq;
   xh[3] = (NTC_FOLD_BIAS && !P::kScaled) ? 1.0f : 0.0f;

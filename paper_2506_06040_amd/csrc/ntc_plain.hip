@@ -111,12 +111,23 @@ __device__ __forceinline__ float pow2_floor(float x) {
 }
 
 // Scales of the E4M3 image, powers of two: s_w = 2^floor(log2(448 /
-// max|W_l|)), s_a = 2^floor(log2(448 / act_amax[l])); stored per layer as
-// (s_a, epilogue, s_w). The epilogue factor maps the accumulator of layer l
-// to the scaled input of layer l + 1 (s_a(l+1) / (s_w s_a)) or, for the
-// last layer, to the pre-activation (1 / (s_w s_a)); being a power of two,
-// the decode applies it as the E8M0 block scale of the layer's matrix
-// instructions, and the packed bias is b s_w s_a times it.
+// max|W_l|)); for the first layer's inputs s_a = 2^floor(log2(448 /
+// max(act_amax[0], 1))) (BC1 latent values reach 1 whatever the calibration
+// saw, so a latent times s_a never leaves E4M3's range); for hidden
+// activations s_a = 2^floor(log2(256 / act_amax[l])), because the decode
+// clamps their scaled values to [0, 256] (ReLU and clamp as one FP16
+// conversion of the value / 256, then the scaled FP16 -> E4M3 conversion).
+// Stored per layer as (s_a, epilogue, s_w). The epilogue factor maps the
+// accumulator of layer l to the next layer's scaled input / 256 (s_a(l + 1)
+// / (256 s_w s_a)) or, for the last layer, to the pre-activation (1 / (s_w
+// s_a)); being a power of two, the decode applies it as the E8M0 block
+// scale of the layer's matrix instructions, and the packed bias is b s_w s_a
+// times it.
+__device__ __forceinline__ float act_scale(float am, int l) {
+  if (l == 0) return pow2_floor(448.0f / fmaxf(am, 1.0f));
+  return am > 0.f ? pow2_floor(256.0f / am) : 1.0f;
+}
+
 __global__ void pack_scales_kernel(PackArgs a) {
   const int l = blockIdx.x;
   const int rows = a.p.dims[l + 1], cols = a.p.dims[l];
@@ -132,13 +143,10 @@ __global__ void pack_scales_kernel(PackArgs a) {
   if (threadIdx.x == 0) {
     const float wm = red[0];
     const float sw = wm > 0.f ? pow2_floor(448.0f / wm) : 1.0f;
-    const float am = a.act_amax[l];
-    const float sa = am > 0.f ? pow2_floor(448.0f / am) : 1.0f;
+    const float sa = act_scale(a.act_amax[l], l);
     float epi;
     if (l + 1 < a.s.n_layers) {
-      const float am2 = a.act_amax[l + 1];
-      const float sa2 = am2 > 0.f ? pow2_floor(448.0f / am2) : 1.0f;
-      epi = sa2 / (sw * sa);
+      epi = act_scale(a.act_amax[l + 1], l + 1) / (256.0f * sw * sa);
     } else {
       epi = 1.0f / (sw * sa);
     }

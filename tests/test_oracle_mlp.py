@@ -211,6 +211,43 @@ def test_fp8_emulation_is_scaled_rounding(oracle_lib):
                           torch.from_numpy(np.clip(a32, -448, 448)).to(torch.float8_e4m3fn).to(torch.float64).numpy())
 
 
+def test_fp8_f16_emulation_is_two_step_rounding(oracle_lib):
+    """FP8_F16: first-layer inputs as in FP8; hidden activations h scaled by
+    s, clamped to [0, 256], rounded to binary16 at 1/256 of that value and
+    then to E4M3. Reference: numpy's float16 cast and torch's float8_e4m3fn
+    cast (exact inputs only), not the oracle's rounding functions."""
+    O = oracle_lib
+    rng = np.random.default_rng(18)
+    dims = (8, 16, 16, 4)
+    Ws = [rng.standard_normal((dims[l + 1], dims[l])) * 0.5 for l in range(3)]
+    bs = [rng.standard_normal(dims[l + 1]) * 0.2 for l in range(3)]
+    x = rng.random((7, 8)).astype(np.float32).astype(np.float64)
+    ws = np.array([128.0, 256.0, 64.0])
+    as_ = np.array([256.0, 512.0, 16.0])  # the third clamps some activations at 256 / 16
+    f = _run_mlp(O, Ws, bs, x, precision=O.FP8_F16, ws=ws, as_=as_)
+
+    def e4m3(v32):
+        return torch.from_numpy(np.asarray(v32, np.float32)).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+
+    h = x.T
+    clamped = 0
+    for l in range(3):
+        qw = np.vectorize(O.round_e4m3_sat)(Ws[l] * ws[l])
+        if l == 0:
+            qa = e4m3(h * as_[l])  # x * 256 is exact in float32 and below 448
+        else:
+            t = np.clip(h * as_[l] / 256.0, 0.0, 1.0)
+            clamped += int((h * as_[l] > 256.0).sum())
+            qa = e4m3(t.astype(np.float16).astype(np.float32) * np.float32(256.0))
+        z = (qw @ qa) / (ws[l] * as_[l]) + bs[l][:, None]
+        h = np.maximum(z, 0) if l < 2 else expit(z)
+    assert clamped > 0
+    assert np.allclose(f, h.T, rtol=1e-13, atol=1e-15)
+    # the two-step rounding differs from one E4M3 rounding somewhere
+    f1 = _run_mlp(O, Ws, bs, x, precision=O.FP8, ws=ws, as_=as_)
+    assert not np.allclose(f, f1, rtol=1e-13, atol=1e-15)
+
+
 def test_layer_amax(oracle_lib):
     O = oracle_lib
     rng = np.random.default_rng(9)
@@ -258,7 +295,9 @@ def test_mlp_forward_batch_vs_brute_force(oracle_lib):
 def test_fp8_scales_closed_forms(oracle_lib):
     """Per-layer E4M3 scales s = 448 / max|.| (weights: largest magnitude of
     the layer's matrix, negative entries included; activations: the
-    calibrated amax), and their power-of-two form 2^floor(log2(448 / max))."""
+    calibrated amax), and their power-of-two form: 2^floor(log2(448 / max))
+    for the weights and the first layer's inputs (whose range always
+    includes [0, 1]), 2^floor(log2(256 / amax)) for hidden activations."""
     O = oracle_lib
     Ws = [np.array([[0.5, -1.0], [0.25, 0.125]]), np.array([[448.0, 1.0]]), np.array([[-2.0, 500.0]]),
           np.array([[3.0, -7.0]])]
@@ -273,6 +312,15 @@ def test_fp8_scales_closed_forms(oracle_lib):
     assert as_[3] == np.float64(np.float32(448.0) / np.float32(0.001))
     w2, a2 = O.fp8_scales(Ws, amax, pow2=True)
     assert list(w2) == [256.0, 1.0, 0.5, 64.0]
-    assert list(a2) == [512.0, 256.0, 1.0, 262144.0]
+    # first layer: 448 / max(0.7, 1) = 448 -> 256; hidden: 256 / 1, 256 / 448, 256 / 0.001
+    assert list(a2) == [256.0, 256.0, 0.5, 131072.0]
     # a power of two never exceeds the plain scale and is at least half of it
-    assert np.all(w2 <= ws) and np.all(w2 > ws / 2) and np.all(a2 <= as_) and np.all(a2 > as_ / 2)
+    assert np.all(w2 <= ws) and np.all(w2 > ws / 2)
+    # hidden scales map the calibrated amax into [128, 256]
+    hid = np.array(amax[1:]) * a2[1:]
+    assert np.all(hid <= 256.0) and np.all(hid > 128.0)
+    # a first layer calibrated at or above 1 keeps the 448 form
+    _, a3 = O.fp8_scales(Ws, [1.5, 1.0, 1.0, 1.0], pow2=True)
+    assert a3[0] == 256.0 and 1.5 * a3[0] <= 448.0
+    _, a4 = O.fp8_scales(Ws, [3.0, 1.0, 1.0, 1.0], pow2=True)
+    assert a4[0] == 128.0
