@@ -105,3 +105,32 @@ def test_random_derivatives_parity():
         print(f"[random duv {filt}] left out {int((~keep).sum())} max err {err:.2e}", flush=True)
         assert (~keep).sum() <= 1e-3 * n
         assert err <= TOL_F16_ABS, filt
+
+
+@pytest.mark.parametrize("filt", ["trilinear", "anisotropic"])
+def test_staged_footprints_equal_direct(filt):
+    """A pixel's result does not depend on its span: coherent rows of a
+    perspective plane (footprints staged in LDS) against the same pixels
+    shuffled (spans whose footprints cover whole levels fetch directly),
+    bit for bit, and against the oracle."""
+    ntc = _ntc()
+    sizes = [(128, 128), (64, 64), (32, 32), (16, 16)]
+    rng, chains, Ws, bs = _case(4, sizes)
+    uv, duv = I.perspective_plane(128, 96, far=12.0)
+    duv = duv * np.float32(1.5)
+    lm, mlp = ntc.LatentMips(chains, shift=I.PAPER_SHIFT), ntc.Mlp(Ws, bs)
+    perm = rng.permutation(uv.shape[0])
+
+    def run(u, d):
+        return ntc.decode_filtered(lm, mlp, torch.from_numpy(np.ascontiguousarray(u)).cuda(),
+                                   torch.from_numpy(np.ascontiguousarray(d)).cuda(), filter=filt, max_aniso=8)
+
+    coherent = run(uv, duv)
+    shuffled = run(uv[perm], duv[perm])
+    assert torch.equal(shuffled, coherent[torch.from_numpy(perm).cuda()])
+    ref = F.decode(chains, I.PAPER_SHIFT, O.Mlp(Ws, bs), uv, duv, filt, 8)
+    keep = ~_ambiguous(sizes, duv, 8) if filt == "anisotropic" else np.ones(uv.shape[0], bool)
+    err = np.abs(coherent.cpu().numpy() - ref)[keep].max()
+    print(f"[staged {filt}] left out {int((~keep).sum())} max err {err:.2e}", flush=True)
+    assert (~keep).sum() <= 1e-3 * uv.shape[0]
+    assert err <= TOL_F16_ABS
