@@ -433,7 +433,7 @@ def main():
                    "pixels": N, "mlp": list(wl.dims)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP16_TFLOPS, 4), "traffic": traffic,
-                     "kernel": "decode_mfma_kernel<PrecF16,64,4,true>",
+                     "kernel": "decode_mfma_kernel<PrecF16,64,4,1>",
                      "flops_per_launch": flops,
                      "hbm_algorithmic_GBs": round(N * 40 / (ms16 * 1e-3) / 1e9, 1)},
         "cpu_baseline": cpu,
