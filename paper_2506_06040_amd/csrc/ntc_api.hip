@@ -358,6 +358,24 @@ ntc_status ntc_decode_filtered(const ntc_latent_mips *lat, const ntc_mlp *mlp, c
       M.w = lat->width[src] >> ms;
       M.h = lat->height[src] >> ms;
       M.bw = M.w / 4;
+      M.fw = (float)M.w;
+      M.fh = (float)M.h;
+    }
+  }
+  // one level-of-detail computation per pixel when every level is level 0
+  // scaled by a power of two on both axes
+  f.shared_lod = 1;
+  for (int k = 0; k < lat->n_levels; ++k) {
+    int e = 0;
+    const int w = lat->width[k], h = lat->height[k], w0 = lat->width[0], h0 = lat->height[0];
+    if (w <= w0) {
+      while ((w << e) < w0) ++e;
+      if ((w << e) != w0 || (h << e) != h0) f.shared_lod = 0;
+      f.lod_shift[k] = (float)e;
+    } else {
+      while ((w0 << e) < w) ++e;
+      if ((w0 << e) != w || (h0 << e) != h) f.shared_lod = 0;
+      f.lod_shift[k] = -(float)e;
     }
   }
   hipError_t e = launch_decode_filtered(f, s, device_cus() * 8, (hipStream_t)stream);

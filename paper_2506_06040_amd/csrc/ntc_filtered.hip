@@ -34,12 +34,12 @@ constexpr int kRegions = 2 * kMaxLevels;
 __device__ __forceinline__ TabLevel mip_level(const FilterArgs &f, int k, int m) {
   const MipArgs &M = f.mip[k][m];
   TabLevel L;
-  L.fw = (float)M.w;
-  L.fh = (float)M.h;
+  L.fw = M.fw;
+  L.fh = M.fh;
   L.cx = f.sx[k] - 0.5f;
   L.cy = f.sy[k] - 0.5f;
-  L.wm2 = (float)(M.w - 2);
-  L.hm2 = (float)(M.h - 2);
+  L.wm2 = M.fw - 2.0f;
+  L.hm2 = M.fh - 2.0f;
   L.w = M.w;
   L.h = M.h;
   L.bw = M.bw;
@@ -59,23 +59,28 @@ struct LodSel {
   float t, du, dv;
 };
 
+// The part of the selection that does not depend on the level's mip count:
+// the unclamped level of detail and, for anisotropic filtering, the tap
+// count and the major axis, from the footprint on a level of w0 x h0 texels.
+struct LodBase {
+  float lod;
+  int n;
+  float du, dv;
+};
+
 template <int FILTER>
-__device__ __forceinline__ LodSel lod_select(const FilterArgs &f, int k, float4 d) {
-  LodSel s;
-  const float w0 = f.w0[k], h0 = f.h0[k];
+__device__ __forceinline__ LodBase lod_base(const FilterArgs &f, float w0, float h0, float4 d) {
+  LodBase b;
   // squared footprint axes in mip-0 texels, each operation rounded once
   const float ax = __fmul_rn(d.x, w0), bx = __fmul_rn(d.y, h0);
   const float ay = __fmul_rn(d.z, w0), by = __fmul_rn(d.w, h0);
   const float px2 = __fadd_rn(__fmul_rn(ax, ax), __fmul_rn(bx, bx));
   const float py2 = __fadd_rn(__fmul_rn(ay, ay), __fmul_rn(by, by));
-  const int nm = f.n_mips[k];
-  const float top = (float)(nm - 1);
-  float lod;
   if (FILTER == 1) {
-    lod = fminf(fmaxf(0.5f * __log2f(fmaxf(px2, py2)), 0.0f), top);  // NaN and -inf give 0
-    s.n = 1;
-    s.du = 0.0f;
-    s.dv = 0.0f;
+    b.lod = 0.5f * __log2f(fmaxf(px2, py2));
+    b.n = 1;
+    b.du = 0.0f;
+    b.dv = 0.0f;
   } else {
     const float pmax2 = fmaxf(px2, py2), pmin2 = fminf(px2, py2);
     int n = f.max_aniso;
@@ -84,17 +89,29 @@ __device__ __forceinline__ LodSel lod_select(const FilterArgs &f, int k, float4 
         n = i;
         break;
       }
-    lod = fminf(fmaxf(0.5f * __log2f(pmax2) - __log2f((float)n), 0.0f), top);
+    b.lod = 0.5f * __log2f(pmax2) - __log2f((float)n);
     const bool major_x = px2 >= py2;
-    s.n = n;
-    s.du = major_x ? d.x : d.z;
-    s.dv = major_x ? d.y : d.w;
+    b.n = n;
+    b.du = major_x ? d.x : d.z;
+    b.dv = major_x ? d.y : d.w;
   }
+  return b;
+}
+
+// Selection on level k from a base whose level of detail is `shift` above
+// this level's.
+__device__ __forceinline__ LodSel lod_select(const FilterArgs &f, int k, const LodBase &b, float shift) {
+  LodSel s;
+  const int nm = f.n_mips[k];
+  const float lod = fminf(fmaxf(b.lod - shift, 0.0f), (float)(nm - 1));  // NaN and -inf give 0
   int m0 = (int)floorf(lod);
   m0 = m0 < 0 ? 0 : (m0 > nm - 1 ? nm - 1 : m0);
   const float t = lod - (float)m0;
   s.m0 = m0;
   s.t = (t > 0.0f && m0 + 1 < nm) ? t : 0.0f;
+  s.n = b.n;
+  s.du = b.du;
+  s.dv = b.dv;
   return s;
 }
 
@@ -126,6 +143,22 @@ __device__ __forceinline__ float3 filter_level(const LodSel &s, float u, float v
   }
   const float inv = 1.0f / (float)s.n;
   return make_float3(acc.x * inv, acc.y * inv, acc.z * inv);
+}
+
+// Trilinear features of one level in packed FP16: the sample of mip m0,
+// blended towards the sample of mip m0 + 1 by t (a subtraction and a fused
+// multiply-add per channel pair; the constant 1 of the (b, 1) pair stays 1).
+template <class SMP>
+__device__ __forceinline__ Tex16 trilinear16(const LodSel &s, float u, float v, SMP &&smp) {
+  Tex16 c = smp(s.m0, u, v);
+  if (s.t > 0.0f) {
+    const Tex16 c1 = smp(s.m0 + 1, u, v);
+    const _Float16 th = (_Float16)s.t;
+    const half2_t t2 = {th, th};
+    c.rg = __builtin_elementwise_fma(t2, c1.rg - c.rg, c.rg);
+    c.b1 = __builtin_elementwise_fma(t2, c1.b1 - c.b1, c.b1);
+  }
+  return c;
 }
 
 // Staged regions of one span: region r = 2 k + j is mip m_lo[k] + j of level
@@ -183,7 +216,7 @@ __device__ __forceinline__ FiltStage stage_footprints(const FilterArgs &f, const
   const bool valid = lane < 4 * kRegions && k < f.n_levels && m < f.n_mips[k];
   const MipArgs &M = f.mip[k][valid ? m : 0];
   const bool ay = q >= 2;
-  const float dim = ay ? (float)M.h : (float)M.w;
+  const float dim = ay ? M.fh : M.fw;
   const float ext = q == 0 ? umin : (q == 1 ? umax : (q == 2 ? vmin : vmax));
   const int ti = (int)tap_floor(ext, dim, (ay ? f.sy[k] : f.sx[k]) - 0.5f, dim - 2.0f);
   // every lane of quad r receives the four values of region r
@@ -275,43 +308,87 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
   W.ready();
   __syncthreads();
   const int64_t n_sub = (a.n + 63) / 64;
+  // this lane's pixel of span s (lanes past the end repeat the last pixel)
+  auto pixel_of = [&](int64_t s) {
+    const int64_t left = a.n - s * 64;
+    return s * 64 + (lane < left ? lane : left - 1);
+  };
+  // uv and derivatives are loaded one span ahead
+  float2 uv_next = make_float2(0.f, 0.f);
+  float4 d_next = make_float4(0.f, 0.f, 0.f, 0.f);
+  if ((int64_t)blockIdx.x < n_sub) {
+    const int64_t p = pixel_of(blockIdx.x);
+    uv_next = a.uv[p];
+    d_next = f.duv[p];
+  }
   for (int64_t s = blockIdx.x; s < n_sub; s += gridDim.x) {
     const int64_t first = s * 64;
     const int64_t left = a.n - first;
-    const int64_t pix = first + (lane < left ? lane : left - 1);
-    const float2 uv = a.uv[pix];
-    const float4 d = f.duv[pix];
+    const float2 uv = uv_next;
+    const float4 d = d_next;
+    if (s + gridDim.x < n_sub) {
+      const int64_t p = pixel_of(s + gridDim.x);
+      uv_next = a.uv[p];
+      d_next = f.duv[p];
+    }
     LodSel sel[kMaxLevels];
+    if (f.shared_lod) {
+      const LodBase b = lod_base<FILTER>(f, f.w0[0], f.h0[0], d);
 #pragma unroll
-    for (int k = 0; k < kMaxLevels; ++k) sel[k] = lod_select<FILTER>(f, k < f.n_levels ? k : 0, d);
+      for (int k = 0; k < kMaxLevels; ++k) sel[k] = lod_select(f, k < f.n_levels ? k : 0, b, f.lod_shift[k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < kMaxLevels; ++k) {
+        const int kk = k < f.n_levels ? k : 0;
+        sel[k] = lod_select(f, kk, lod_base<FILTER>(f, f.w0[kk], f.h0[kk], d), 0.0f);
+      }
+    }
     const FiltStage st = stage_footprints<FILTER>(f, sel, uv.x, uv.y, stage, srec, (int)s);
+    typename P::Frag bx[2];
+    Tex16 c16[kMaxLevels];
     float xl[8], xh[8];
 #pragma unroll
     for (int k = 0; k < kMaxLevels; ++k) {
+      // levels past n_levels: zero features (their (b, 1) pads keep the
+      // constant 1 of the bias slots)
+      const half2_t z = {(_Float16)0.0f, (_Float16)0.0f}, z1 = {(_Float16)0.0f, (_Float16)1.0f};
+      c16[k].rg = z;
+      c16[k].b1 = z1;
       float3 c = make_float3(0.f, 0.f, 0.f);
       if (k < f.n_levels) {
-        // this level's two staged regions, as uniform values
+        // this level's staged regions (the span's lowest mip m_lo and
+        // m_lo + 1), as wave-uniform values
         const bool s0 = (st.staged >> (2 * k)) & 1u, s1 = (st.staged >> (2 * k + 1)) & 1u;
-        const int mlo = st.m_lo[k];
-        const float cx = f.sx[k] - 0.5f, cy = f.sy[k] - 0.5f;
+        const int mlo = __builtin_amdgcn_readfirstlane(st.m_lo[k]);
         const MipArgs &M0 = f.mip[k][mlo];
         const MipArgs &M1 = f.mip[k][mlo + 1 < kMaxMips ? mlo + 1 : mlo];
-        const float w0 = (float)M0.w, h0 = (float)M0.h, w1 = (float)M1.w, h1 = (float)M1.h;
-        auto smp = [&](int m, float x, float y) -> float3 {
+        const float cx = f.sx[k] - 0.5f, cy = f.sy[k] - 0.5f;
+        const int kbw0 = st.kbw[2 * k], kbw1 = st.kbw[2 * k + 1];
+        const int kb0 = st.kbase[2 * k], kb1 = st.kbase[2 * k + 1];
+        // sample of mip m at (x, y): from a staged region or fetched directly
+        auto smp = [&](int m, float x, float y) -> Tex16 {
           const int j = m - mlo;
           if ((j == 0 && s0) || (j == 1 && s1)) {
             const bool one = j == 1;
-            return tex_f3(staged_sample(stage, one ? w1 : w0, one ? h1 : h0, cx, cy, one ? st.kbw[2 * k + 1] : st.kbw[2 * k],
-                                        one ? st.kbase[2 * k + 1] : st.kbase[2 * k], x, y));
+            return staged_sample(stage, one ? M1.fw : M0.fw, one ? M1.fh : M0.fh, cx, cy, one ? kbw1 : kbw0,
+                                 one ? kb1 : kb0, x, y);
           }
-          return tex_f3(sample_direct16(mip_level(f, k, m), tap_coord(x), tap_coord(y), 0));
+          return sample_direct16(mip_level(f, k, m), tap_coord(x), tap_coord(y), 0);
         };
-        c = filter_level<FILTER>(sel[k], uv.x, uv.y, smp);
+        if constexpr (FILTER == 1)
+          c16[k] = trilinear16(sel[k], uv.x, uv.y, smp);
+        else
+          c = filter_level<FILTER>(sel[k], uv.x, uv.y, [&](int m, float x, float y) { return tex_f3(smp(m, x, y)); });
       }
-      put_level(xl, xh, k, c);
+      if constexpr (FILTER != 1) put_level(xl, xh, k, c);
     }
-    typename P::Frag bx[2];
-    pixel_operands<P>(xl, xh, uv.x, uv.y, W.in_scale, bx);
+    if constexpr (FILTER == 1) {
+      // trilinear: FP16 samples blended in packed FP16 straight into the
+      // first layer's operands
+      operands16(c16, uv.x, uv.y, bx);
+    } else {
+      pixel_operands<P>(xl, xh, uv.x, uv.y, W.in_scale, bx);
+    }
     const int span = left < 64 ? (int)left : 64;
     subspan_mlp<P, HID, NL, VEC4, false>(a, W, bias, span_out(a, first, span), bx, 0, (int)first);
   }

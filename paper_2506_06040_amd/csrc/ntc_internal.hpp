@@ -195,7 +195,9 @@ constexpr int kMaxMips = 12;
 constexpr int kMaxAniso = 16;
 struct MipArgs {
   const uint2 *bc1;
-  int32_t w, h, bw, pad_;
+  int32_t w, h, bw;
+  float fw, fh;  // w and h as floats
+  int32_t pad_;
 };
 struct FilterArgs {
   DecodeArgs d;            // packed image, uv, out, n, shapes (d.lat is unused)
@@ -204,7 +206,12 @@ struct FilterArgs {
   int32_t n_mips[kMaxLevels];
   float w0[kMaxLevels], h0[kMaxLevels];  // mip 0 sizes
   float sx[kMaxLevels], sy[kMaxLevels];  // shifts in texels of each mip
-  int32_t n_levels, filter, max_aniso, pad_;
+  // shared_lod: every level's mip 0 is level 0's mip 0 scaled by 2^-e_k on
+  // both axes (lod_shift[k] = e_k), so its squared footprint axes are level
+  // 0's times 4^-e_k exactly and its level of detail is level 0's minus e_k
+  float lod_shift[kMaxLevels];
+  int32_t shared_lod;
+  int32_t n_levels, filter, max_aniso;
 };
 hipError_t launch_decode_filtered(const FilterArgs &f, const MlpShape &s, int grid_waves, hipStream_t st);
 
