@@ -134,3 +134,27 @@ def test_staged_footprints_equal_direct(filt):
     print(f"[staged {filt}] left out {int((~keep).sum())} max err {err:.2e}", flush=True)
     assert (~keep).sum() <= 1e-3 * uv.shape[0]
     assert err <= TOL_F16_ABS
+
+
+@pytest.mark.parametrize("filt", ["trilinear", "anisotropic"])
+def test_unrelated_level_sizes(filt):
+    """Levels that are not powers of two of each other (96^2 with 4 mips,
+    64x32, 40^2 with 2 mips): each level takes its own level of detail."""
+    ntc = _ntc()
+    rng = np.random.default_rng(6)
+    specs = [(96, 96, 4), (64, 32, 0), (40, 40, 2)]
+    chains = [I.bc1_mip_chain(rng, w, h, m) for (w, h, m) in specs]
+    sizes = [(w, h) for (w, h, _) in specs]
+    Ws, bs = I.xavier_mlp(rng, (11, 32, 32, 8), bias="normal")
+    n = 4000
+    uv = (rng.random((n, 2)) * 1.2 - 0.1).astype(np.float32)
+    duv = (rng.standard_normal((n, 4)) * np.exp(rng.uniform(-7, -1, (n, 1)))).astype(np.float32)
+    shift = I.PAPER_SHIFT[:3]
+    out = ntc.decode_filtered(ntc.LatentMips(chains, shift=shift), ntc.Mlp(Ws, bs), torch.from_numpy(uv).cuda(),
+                              torch.from_numpy(duv).cuda(), filter=filt, max_aniso=8).cpu().numpy()
+    ref = F.decode(chains, shift, O.Mlp(Ws, bs), uv, duv, filt, 8)
+    keep = ~_ambiguous(sizes, duv, 8) if filt == "anisotropic" else np.ones(n, bool)
+    err = np.abs(out - ref)[keep].max()
+    print(f"[unrelated sizes {filt}] left out {int((~keep).sum())} max err {err:.2e}", flush=True)
+    assert (~keep).sum() <= 1e-3 * n
+    assert err <= TOL_F16_ABS
