@@ -390,7 +390,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
       pixel_operands<P>(xl, xh, uv.x, uv.y, W.in_scale, bx);
     }
     const int span = left < 64 ? (int)left : 64;
-    subspan_mlp<P, HID, NL, VEC4, false>(a, W, bias, span_out(a, first, span), bx, 0, (int)first);
+    // ReLU by the [0, 1] clamp of the conversion when the image is scaled
+    // for it and every coordinate of the span lies in the unit square (the
+    // features are then blends of latent values in [0, 1], as in the
+    // unfiltered decode)
+    const bool in_unit =
+        __builtin_amdgcn_ballot_w64(!(uv.x >= 0.0f && uv.x <= 1.0f && uv.y >= 0.0f && uv.y <= 1.0f)) == 0;
+    if (in_unit && W.unit_relu != 0)
+      subspan_mlp<P, HID, NL, VEC4, true>(a, W, bias, span_out(a, first, span), bx, 0, (int)first);
+    else
+      subspan_mlp<P, HID, NL, VEC4, false>(a, W, bias, span_out(a, first, span), bx, 0, (int)first);
   }
 }
 
