@@ -61,10 +61,13 @@ def algorithmic_flops_per_px(dims):
     return 2 * sum(dims[i] * dims[i + 1] for i in range(len(dims) - 1))
 
 
-def time_launches(fn, steps, warmup):
+def time_launches(fn, steps, warmup, settle_s=0.3):
     """Average milliseconds per call of fn (launches on the current stream),
-    measured with HIP events around `steps` calls after `warmup` calls."""
+    measured with HIP events around `steps` calls after the clock has
+    settled under fn (settle_s seconds) and `warmup` calls."""
     import torch
+    if settle_s > 0:
+        settle(fn, settle_s)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
