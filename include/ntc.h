@@ -166,8 +166,10 @@ ntc_status ntc_calibrate_fp8(const ntc_latents *lat, const ntc_mlp *mlp, const v
                              const float *uv, int64_t n, float *act_amax, void *stream);
 
 /* Fused decode (Sec. 3.1 + Sec. 3.3 + Sec. 4): out[s] = f(x(uv[s])) for
- * s < n. compute selects the arithmetic: NTC_F32 (plain FP32 FMAs, one
- * pixel per lane), NTC_F16 (FP16 matrix cores, FP32 accumulation),
+ * s < n. compute selects the arithmetic: NTC_F32 (FP32: plain FMAs, one
+ * pixel per lane, for BC1 latents; FP32 matrix cores, 32 samples per step,
+ * for float latents and at most 4 layers), NTC_F16 (FP16 matrix cores, FP32
+ * accumulation),
  * NTC_BF16 (BF16 matrix cores, FP32 accumulation) or NTC_FP8_E4M3 (E4M3
  * matrix cores with per-layer scales, FP32 accumulation). packed is the image written by ntc_mlp_pack for the same
  * compute type. uv float [n][2] [device, 8-byte aligned]; out [n][C]

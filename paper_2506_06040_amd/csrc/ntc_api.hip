@@ -271,7 +271,9 @@ ntc_status ntc_decode(const ntc_latents *lat, const ntc_mlp *mlp, int32_t comput
   a.lay = pack_layout(s, compute);
   const int cus = device_cus();
   hipError_t e;
-  if (compute == NTC_F32)
+  if (compute == NTC_F32 && lat->format == NTC_LATENT_F32 && s.n_layers <= 4)
+    e = launch_forward_f32(a, s, (hipStream_t)stream);
+  else if (compute == NTC_F32)
     e = launch_decode_plain(a, s, nullptr, cus, (hipStream_t)stream);
   else
     e = launch_decode_mfma(a, s, compute, cus * waves_per_cu, (hipStream_t)stream);

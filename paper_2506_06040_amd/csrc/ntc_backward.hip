@@ -719,6 +719,166 @@ __global__ __launch_bounds__(256) void scatter_direct_kernel(BackwardArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Forward decode of continuous (float) latents on the FP32 matrix cores: the
+// forward half of backward_mfma_kernel (same LDS weight layout, same
+// 32-sample steps), ending in the sigmoid and the store. Weights come from
+// the packed FP32 image (per layer W [rows_pad][cols_pad], then b).
+// ---------------------------------------------------------------------------
+template <int MT, int NL>
+__global__ __launch_bounds__(64 * kBwdWaves) void forward_mfma_kernel(DecodeArgs a) {
+  using M = BwdMap<MT, NL>;
+  constexpr int HP = M::HP;
+  extern __shared__ float fwd_lds[];
+  float *lds = fwd_lds;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, h = lane >> 5, c32 = lane & 31;
+  const int wave = tid >> 6;
+  const PackLayout &L = a.lay;
+  const int n_out = a.n_out, n_levels = a.lat.n_levels;
+  const float *W0 = reinterpret_cast<const float *>(a.packed + L.w_off[0]);
+  const float *B0 = reinterpret_cast<const float *>(a.packed + L.b_off[0]);
+  const int hid = L.rows_pad[0] < HP ? L.rows_pad[0] : HP;  // padded rows hold zero weights
+
+  for (int i = tid; i < HP * 16; i += 64 * kBwdWaves) {
+    const int row = i >> 4, k = i & 15;
+    const int f = slot_feature(k >> 1, k & 1, n_levels);
+    float v = 0.0f;
+    if (row < hid) v = f >= 0 ? W0[row * L.cols_pad[0] + f] : (f == -2 ? B0[row] : 0.0f);
+    lds[M::oW0 + row * M::S0 + k] = v;
+  }
+#pragma unroll
+  for (int l = 1; l <= M::NH; ++l) {
+    const float *Wl = reinterpret_cast<const float *>(a.packed + L.w_off[l]);
+    for (int i = tid; i < HP * HP; i += 64 * kBwdWaves) {
+      const int row = i / HP, col = i % HP;
+      lds[M::oWh + (l - 1) * HP * M::SH + row * M::SH + col] =
+          (row < L.rows_pad[l] && col < L.cols_pad[l]) ? Wl[row * L.cols_pad[l] + col] : 0.0f;
+    }
+  }
+  {
+    const float *Wo = reinterpret_cast<const float *>(a.packed + L.w_off[NL - 1]);
+    for (int i = tid; i < 32 * HP; i += 64 * kBwdWaves) {
+      const int row = i / HP, col = i % HP;
+      lds[M::oWo + row * M::SH + col] =
+          (row < L.rows_pad[NL - 1] && col < L.cols_pad[NL - 1]) ? Wo[row * L.cols_pad[NL - 1] + col] : 0.0f;
+    }
+  }
+  for (int i = tid; i < M::nB; i += 64 * kBwdWaves) {
+    const int g = i / 32, e = i % 32;  // g = (l - 1) MT + mt, e = 16 h + 4 j + r
+    const int l = g / MT + 1 < NL - 1 ? g / MT + 1 : NL - 1;
+    const int mt = l == NL - 1 ? 0 : g % MT;
+    const int row = 32 * mt + 8 * ((e & 15) >> 2) + 4 * (e >> 4) + (e & 3);
+    const float *Bl = reinterpret_cast<const float *>(a.packed + L.b_off[l]);
+    lds[M::oB + i] = row < L.rows_pad[l] ? Bl[row] : 0.0f;
+  }
+  __syncthreads();
+
+  const float *W0s = lds + M::oW0;
+  const float *Wos = lds + M::oWo;
+  const bf32x16 zero = {};
+  const int64_t n_chunks = (a.n + kBwdChunk - 1) / kBwdChunk;
+  const int64_t stride = (int64_t)gridDim.x * kBwdWaves;
+  for (int64_t chunk = (int64_t)blockIdx.x * kBwdWaves + wave; chunk < n_chunks; chunk += stride) {
+    const int64_t smp = chunk * kBwdChunk + c32;
+    const bool valid = smp < a.n;
+    const float2 uv = a.uv[valid ? smp : a.n - 1];
+    float x[8];
+    {
+      const float3 c0 = sample_f32(a.lat.lv[2 * h], uv.x, uv.y, a.lat.address);
+      const float3 c1 = sample_f32(a.lat.lv[2 * h + 1], uv.x, uv.y, a.lat.address);
+      x[0] = c0.x; x[1] = c0.y; x[2] = c0.z;
+      x[3] = c1.x; x[4] = c1.y; x[5] = c1.z;
+      x[6] = h ? uv.y : uv.x;
+      x[7] = h ? 0.0f : 1.0f;
+    }
+    bf32x16 act[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      bf32x16 z = zero;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) z = mfma32(W0s[(32 * mt + c32) * M::S0 + 2 * s + h], x[s], z);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) z[i] = fmaxf(z[i], 0.0f);
+      act[mt] = z;
+    }
+#pragma unroll
+    for (int l = 1; l <= M::NH; ++l) {
+      const float *Wl = lds + M::oWh + (l - 1) * HP * M::SH;
+      bf32x16 nx[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const bf32x4 *bp = reinterpret_cast<const bf32x4 *>(lds + M::bias(l, mt) + 16 * h);
+        const bf32x4 b0 = bp[0], b1 = bp[1], b2 = bp[2], b3 = bp[3];
+        bf32x16 z = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3],
+                     b2[0], b2[1], b2[2], b2[3], b3[0], b3[1], b3[2], b3[3]};
+#pragma unroll
+        for (int s = 0; s < 16 * MT; ++s)
+          z = mfma32(Wl[(32 * mt + c32) * M::SH + chain_unit(s, h)], act[s >> 4][s & 15], z);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) z[i] = fmaxf(z[i], 0.0f);
+        nx[mt] = z;
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) act[mt] = nx[mt];
+    }
+    const bf32x4 *bp = reinterpret_cast<const bf32x4 *>(lds + M::bias(NL - 1, 0) + 16 * h);
+    const bf32x4 b0 = bp[0], b1 = bp[1];
+    bf32x16 z = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3], 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 16 * MT; ++s) z = mfma32(Wos[c32 * M::SH + chain_unit(s, h)], act[s >> 4][s & 15], z);
+    if (valid) {
+      // rows 8 j + 4 h + r (j < 2, r < 4) of this lane's sample
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int row0 = 8 * j + 4 * h;
+        if (row0 >= n_out) continue;
+        float f[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) f[r] = 1.0f / (1.0f + expf(-z[4 * j + r]));
+        if (a.out_f16) {
+          _Float16 *o = reinterpret_cast<_Float16 *>(a.out) + smp * n_out + row0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (row0 + r < n_out) o[r] = (_Float16)f[r];
+        } else {
+          float *o = reinterpret_cast<float *>(a.out) + smp * n_out + row0;
+          if ((n_out & 3) == 0) {
+            *reinterpret_cast<float4 *>(o) = make_float4(f[0], f[1], f[2], f[3]);
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (row0 + r < n_out) o[r] = f[r];
+          }
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_forward_f32(const DecodeArgs &a, const MlpShape &s, hipStream_t st) {
+  const int groups = backward_groups(a.n);
+  auto go = [&](auto kernel, size_t floats) {
+    hipLaunchKernelGGL(kernel, dim3(groups), dim3(64 * kBwdWaves), floats * sizeof(float), st, a);
+    return hipGetLastError();
+  };
+  const int mt = s.hid > 32 ? 2 : 1;
+  if (mt == 1) {
+    switch (s.n_layers) {
+      case 2: return go(forward_mfma_kernel<1, 2>, BwdMap<1, 2>::oStage);
+      case 3: return go(forward_mfma_kernel<1, 3>, BwdMap<1, 3>::oStage);
+      case 4: return go(forward_mfma_kernel<1, 4>, BwdMap<1, 4>::oStage);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (s.n_layers) {
+    case 2: return go(forward_mfma_kernel<2, 2>, BwdMap<2, 2>::oStage);
+    case 3: return go(forward_mfma_kernel<2, 3>, BwdMap<2, 3>::oStage);
+    case 4: return go(forward_mfma_kernel<2, 4>, BwdMap<2, 4>::oStage);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_backward(const BackwardArgs &a, const MlpShape &s, float *const *grad_W, float *const *grad_b,
                            hipStream_t st) {
   // latent gradients start at zero (fill kernel: no memset nodes in graphs)

@@ -86,6 +86,8 @@ struct DecodeArgs {
 hipError_t launch_decode_plain(const DecodeArgs &a, const MlpShape &s, float *calib_amax, int n_cus,
                                hipStream_t st);
 hipError_t launch_decode_mfma(const DecodeArgs &a, const MlpShape &s, int compute, int grid_waves, hipStream_t st);
+// FP32 decode of float latents on the matrix cores (up to 4 layers).
+hipError_t launch_forward_f32(const DecodeArgs &a, const MlpShape &s, hipStream_t st);
 int decode_span_tiles();  // 64-pixel tiles per span of the matrix-core decode
 hipError_t launch_bc1_texels(const LevelArgs &L, float *out, uint16_t *numer, hipStream_t st);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);

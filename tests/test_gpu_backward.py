@@ -221,3 +221,35 @@ def test_backward_weight_gradients_repeatable():
         assert np.array_equal(a[1][l], b[1][l]), f"db{l}"
     for k in range(4):
         _close(f"repeat dlat{k}", a[2][k], b[2][k], rtol=1e-5)
+
+
+@pytest.mark.parametrize("dims,sizes,address", [
+    ((14, 64, 64, 8), [(64, 64), (32, 32), (16, 16), (8, 8)], "clamp"),
+    ((14, 32, 32, 32, 8), [(48, 40), (24, 20), (12, 10), (8, 8)], "wrap"),
+    ((11, 16, 5), [(40, 40), (20, 20), (16, 8)], "clamp"),
+    ((5, 64, 64, 64, 16), [(32, 32)], "clamp"),
+    ((8, 32, 3), [(16, 16), (8, 8)], "wrap"),
+])
+def test_forward_float_latents(dims, sizes, address):
+    """FP32 decode of float latents (the training forward, on the FP32
+    matrix cores) against the oracle: FP32 out within 1e-5 relative of every
+    value, FP16 out within FP16 rounding of it; ragged and tiny batches."""
+    ntc = _ntc()
+    rng = np.random.default_rng(37 + dims[1] + len(dims))
+    lat_np = I.f32_pyramid(rng, sizes)
+    Ws, bs = I.xavier_mlp(rng, dims, bias="normal")
+    shift = I.PAPER_SHIFT[:len(sizes)]
+    lat = ntc.Latents(lat_np, shift=shift, address=address)
+    mlp = ntc.Mlp(Ws, bs)
+    olat = O.Latents(lat_np, shift=shift, address=O.WRAP if address == "wrap" else O.CLAMP)
+    omlp = O.Mlp(Ws, bs)
+    for n in (1, 33, 5003):
+        uv = (rng.random((n, 2)) * 1.4 - 0.2).astype(np.float32)
+        ref = O.decode(olat, omlp, uv)
+        out = ntc.decode(lat, mlp, torch.from_numpy(uv).cuda(), compute="f32").cpu().numpy()
+        assert out.shape == ref.shape
+        assert np.all(np.abs(out - ref) <= 1e-5 * np.abs(ref)), (n, float(np.max(np.abs(out - ref) / np.abs(ref))))
+        o16 = ntc.decode(lat, mlp, torch.from_numpy(uv).cuda(), compute="f32",
+                         out_dtype=torch.float16).cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(o16 - ref) <= 2.0 ** -11 * np.abs(ref) + 1e-7), n
+    print(f"[forward float latents {dims} {address}] ok", flush=True)
