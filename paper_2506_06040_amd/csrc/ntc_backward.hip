@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 
 #include "ntc_device.hpp"
 #include "ntc_internal.hpp"
@@ -612,14 +613,75 @@ __device__ __forceinline__ void window_axis(float p_lo, float p_hi, bool open_lo
   nc = hi - lo + 1;
 }
 
+// Sub-bin of a sample inside its bin: 8 x 8 squares of bin_tex / 8 level-0
+// texels (the same clamped position as bin_of).
+__device__ __forceinline__ int sub_of(const BackwardArgs &a, float2 uv, int bx, int by) {
+  const LevelArgs &L = a.lat.lv[0];
+  float x = fmaf(uv.x, L.fw, -0.5f) + L.sx;
+  float y = fmaf(uv.y, L.fh, -0.5f) + L.sy;
+  x = fminf(fmaxf(x, 0.0f), L.fw - 1.0f);
+  y = fminf(fmaxf(y, 0.0f), L.fh - 1.0f);
+  const int st = a.bin_tex >> 3;
+  const int sx = min(((int)x - bx * a.bin_tex) / st, 7), sy = min(((int)y - by * a.bin_tex) / st, 7);
+  return 8 * max(sy, 0) + max(sx, 0);
+}
+
+// Bilinear-tap gradients of one level, accumulated while consecutive samples
+// keep the same taps (a lane walks the samples of one sub-bin, which share
+// the taps of the coarse levels most of the time) and added to the LDS
+// window (or, outside it, to the gradient texture) when they change.
+struct TapCache {
+  int ix, iy;      // unclamped left / top tap of the cached contributions
+  float g[4][3];   // per tap, per channel
+};
+
+__device__ __forceinline__ void cache_flush(TapCache &c, const BackwardArgs &a, int k, const BinWindow &wk,
+                                            float *win) {
+  if (c.ix == INT_MIN) return;
+  const LevelArgs &L = a.lat.lv[k];
+  const int i0 = address_coord(c.ix, L.w, 0), i1 = address_coord(c.ix + 1, L.w, 0);
+  const int j0 = address_coord(c.iy, L.h, 0), j1 = address_coord(c.iy + 1, L.h, 0);
+  const int ii[4] = {i0, i1, i0, i1};
+  const int jj[4] = {j0, j0, j1, j1};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int col = ii[q] - wk.c0, row = jj[q] - wk.r0;
+    if (wk.lds >= 0 && (unsigned)col < (unsigned)wk.nc && (unsigned)row < (unsigned)wk.nr) {
+      float *p = win + wk.lds + 3 * (row * wk.nc + col);
+      atomicAdd(p + 0, c.g[q][0]);
+      atomicAdd(p + 1, c.g[q][1]);
+      atomicAdd(p + 2, c.g[q][2]);
+    } else {
+      float *p = a.grad_lat[k] + ((int64_t)jj[q] * L.w + ii[q]) * 3;
+      unsafeAtomicAdd(p + 0, c.g[q][0]);
+      unsafeAtomicAdd(p + 1, c.g[q][1]);
+      unsafeAtomicAdd(p + 2, c.g[q][2]);
+    }
+  }
+  c.ix = INT_MIN;
+}
+
+// One bin per workgroup. The bin's samples are sorted by sub-bin in LDS (in
+// rounds of kBinChunk); thread t then walks the samples of sub-bin t % 64
+// with stride 4 (t / 64 the phase), so the 64 lanes of a wavefront work in
+// 64 different places of the bin and each lane's consecutive samples are
+// neighbours. LDS: the texel windows (bin_lds floats), then the sorted
+// sample indices and the sub-bin counts.
+constexpr int kBinChunk = 2048;
+constexpr int kSubBins = 64;
+
 __global__ __launch_bounds__(256) void bin_accum_kernel(BackwardArgs a) {
   extern __shared__ float win[];
+  int32_t *sorted = reinterpret_cast<int32_t *>(win + a.bin_lds);
+  int32_t *sub_start = sorted + kBinChunk;      // [kSubBins + 1]
+  int32_t *sub_cursor = sub_start + kSubBins + 1;  // [kSubBins]
   const int bin = blockIdx.x;
   const int start = a.bin_count[bin];
   const int end = bin + 1 < a.n_bins ? a.bin_count[bin + 1] : (int)a.n;
   if (start >= end) return;
   const int bx = bin % a.bins_x, by = bin / a.bins_x;
   const int n_levels = a.lat.n_levels;
+  const int tid = threadIdx.x;
   BinWindow wk[kMaxLevels];
   int used = 0;
   const LevelArgs &L0 = a.lat.lv[0];
@@ -640,48 +702,84 @@ __global__ __launch_bounds__(256) void bin_accum_kernel(BackwardArgs a) {
       }
     }
   }
-  for (int i = threadIdx.x; i < used; i += 256) win[i] = 0.0f;
-  __syncthreads();
-  for (int i = start + threadIdx.x; i < end; i += 256) {
-    const int s = a.perm[i];
-    const float2 uv = a.uv[s];
-    const float *g = a.dx + (int64_t)s * a.n_feat;
+  for (int i = tid; i < used; i += 256) win[i] = 0.0f;
+  const int sub = tid & (kSubBins - 1), phase = tid >> 6;
+  for (int c0 = start; c0 < end; c0 += kBinChunk) {
+    const int m = min(kBinChunk, end - c0);
+    // counting sort of this round's samples by sub-bin
+    if (tid <= kSubBins) sub_start[tid] = 0;
+    __syncthreads();
+    for (int i = tid; i < m; i += 256) atomicAdd(&sub_start[1 + sub_of(a, a.uv[a.perm[c0 + i]], bx, by)], 1);
+    __syncthreads();
+    if (tid < 64) {  // inclusive scan of the 64 counts (one wavefront)
+      int v = sub_start[1 + tid];
 #pragma unroll
-    for (int k = 0; k < kMaxLevels; ++k) {
-      if (k < n_levels) {
-        const LevelArgs &L = a.lat.lv[k];
-        const Taps t = tap_coords(uv.x, uv.y, L, 0);
-        const float gx = 1.0f - t.fx, gy = 1.0f - t.fy;
-        const float w[4] = {gx * gy, t.fx * gy, gx * t.fy, t.fx * t.fy};
-        const int ii[4] = {t.i0, t.i1, t.i0, t.i1};
-        const int jj[4] = {t.j0, t.j0, t.j1, t.j1};
-        const float d0 = g[3 * k], d1 = g[3 * k + 1], d2 = g[3 * k + 2];
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (tid >= o) v += t;
+      }
+      sub_start[1 + tid] = v;
+    }
+    __syncthreads();
+    if (tid < kSubBins) sub_cursor[tid] = sub_start[tid];
+    __syncthreads();
+    for (int i = tid; i < m; i += 256) {
+      const int s = a.perm[c0 + i];
+      const int key = sub_of(a, a.uv[s], bx, by);
+      sorted[atomicAdd(&sub_cursor[key], 1)] = s;
+    }
+    __syncthreads();
+    // this thread's samples: sub-bin `sub`, every fourth
+    TapCache cache[kMaxLevels];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int c = ii[q] - wk[k].c0, r = jj[q] - wk[k].r0;
-          if (wk[k].lds >= 0 && (unsigned)c < (unsigned)wk[k].nc && (unsigned)r < (unsigned)wk[k].nr) {
-            float *p = win + wk[k].lds + 3 * (r * wk[k].nc + c);
-            atomicAdd(p + 0, w[q] * d0);
-            atomicAdd(p + 1, w[q] * d1);
-            atomicAdd(p + 2, w[q] * d2);
-          } else {
-            float *p = a.grad_lat[k] + ((int64_t)jj[q] * L.w + ii[q]) * 3;
-            unsafeAtomicAdd(p + 0, w[q] * d0);
-            unsafeAtomicAdd(p + 1, w[q] * d1);
-            unsafeAtomicAdd(p + 2, w[q] * d2);
+    for (int k = 0; k < kMaxLevels; ++k) cache[k].ix = INT_MIN;
+    const int j1 = sub_start[sub + 1];
+    for (int j = sub_start[sub] + phase; j < j1; j += 4) {
+      const int s = sorted[j];
+      const float2 uv = a.uv[s];
+      const float *g = a.dx + (int64_t)s * a.n_feat;
+#pragma unroll
+      for (int k = 0; k < kMaxLevels; ++k) {
+        if (k < n_levels) {
+          const LevelArgs &L = a.lat.lv[k];
+          float x = fmaf(uv.x, L.fw, -0.5f) + L.sx;
+          float y = fmaf(uv.y, L.fh, -0.5f) + L.sy;
+          x = fminf(fmaxf(x, -16777216.0f), 16777216.0f);
+          y = fminf(fmaxf(y, -16777216.0f), 16777216.0f);
+          const float xf = floorf(x), yf = floorf(y);
+          const float fx = x - xf, fy = y - yf;
+          const int ix = (int)xf, iy = (int)yf;
+          if (ix != cache[k].ix || iy != cache[k].iy) {
+            cache_flush(cache[k], a, k, wk[k], win);
+            cache[k].ix = ix;
+            cache[k].iy = iy;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+              for (int ch = 0; ch < 3; ++ch) cache[k].g[q][ch] = 0.0f;
           }
+          const float gx = 1.0f - fx, gy = 1.0f - fy;
+          const float w[4] = {gx * gy, fx * gy, gx * fy, fx * fy};
+          const float d[3] = {g[3 * k], g[3 * k + 1], g[3 * k + 2]};
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) cache[k].g[q][ch] = fmaf(w[q], d[ch], cache[k].g[q][ch]);
         }
       }
     }
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k)
+      if (k < n_levels) cache_flush(cache[k], a, k, wk[k], win);
+    __syncthreads();
   }
-  __syncthreads();
 #pragma unroll
   for (int k = 0; k < kMaxLevels; ++k) {
     if (k < n_levels && wk[k].lds >= 0) {
       const int nc = wk[k].nc, cnt = 3 * nc * wk[k].nr;
       float *G = a.grad_lat[k];
       const int w = a.lat.lv[k].w;
-      for (int i = threadIdx.x; i < cnt; i += 256) {
+      for (int i = tid; i < cnt; i += 256) {
         const float v = win[wk[k].lds + i];
         if (v != 0.0f) {
           const int texel = i / 3, ch = i - 3 * texel;
@@ -936,7 +1034,8 @@ hipError_t launch_backward(const BackwardArgs &a, const MlpShape &s, float *cons
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(bin_scatter_kernel, dim3(grid), dim3(256), 2 * a.n_bins * sizeof(int32_t), st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(bin_accum_kernel, dim3(a.n_bins), dim3(256), (size_t)a.bin_lds * sizeof(float), st, a);
+  hipLaunchKernelGGL(bin_accum_kernel, dim3(a.n_bins), dim3(256),
+                     (size_t)a.bin_lds * sizeof(float) + (kBinChunk + 2 * kSubBins + 1) * sizeof(int32_t), st, a);
   return hipGetLastError();
 }
 

@@ -107,6 +107,34 @@ def test_backward_wrap_addressing():
     assert np.all(ol[0][0] != 0) and np.all(ol[0][:, 0] != 0)
 
 
+def test_backward_clustered_samples():
+    """Most samples inside one spatial bin of the latent-gradient scatter (its
+    samples are sorted in several rounds), the rest spread: against the
+    oracle."""
+    rng = np.random.default_rng(41)
+    sizes = [(128, 128), (64, 64), (32, 32), (16, 16)]
+    lat_np = I.f32_pyramid(rng, sizes)
+    Ws, bs = I.xavier_mlp(rng, (14, 32, 32, 8), bias="normal")
+    hot = 0.3 + rng.random((12000, 2)) * (30.0 / 128.0)
+    uv = np.concatenate([hot, rng.random((3000, 2))]).astype(np.float32)
+    uv = uv[rng.permutation(uv.shape[0])]
+    olat = O.Latents(lat_np, shift=I.PAPER_SHIFT)
+    omlp = O.Mlp(Ws, bs)
+    amb = relu_ambiguous(olat, Ws, bs, uv, lat_np)
+    print(f"[clustered] ambiguous samples: {int(amb.sum())} of {uv.shape[0]}", flush=True)
+    assert amb.sum() <= AMBIGUOUS_MAX_FRACTION * uv.shape[0]
+    g = rng.standard_normal((uv.shape[0], 8)) * 1e-3
+    g[amb] = 0.0
+    g = g.astype(np.float32).astype(np.float64)
+    gW, gb, gl = _gpu_direct(lat_np, Ws, bs, uv, g, I.PAPER_SHIFT)
+    oW, ob, ol = O.backward(olat, omlp, uv, g)
+    for l in range(3):
+        _close(f"clustered dW{l}", gW[l], oW[l])
+        _close(f"clustered db{l}", gb[l], ob[l])
+    for k in range(4):
+        _close(f"clustered dlat{k}", gl[k], ol[k])
+
+
 @pytest.fixture(scope="module")
 def c3():
     wl = I.WORKLOADS["c3"]
