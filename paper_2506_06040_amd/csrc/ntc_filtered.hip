@@ -57,6 +57,7 @@ __device__ __forceinline__ float3 tex_f3(Tex16 c) {
 struct LodSel {
   int m0, n;
   float t, du, dv;
+  float inv;  // 1 / (n + 1)
 };
 
 // The part of the selection that does not depend on the level's mip count:
@@ -66,6 +67,7 @@ struct LodBase {
   float lod;
   int n;
   float du, dv;
+  float inv;  // 1 / (n + 1)
 };
 
 template <int FILTER>
@@ -81,6 +83,7 @@ __device__ __forceinline__ LodBase lod_base(const FilterArgs &f, float w0, float
     b.n = 1;
     b.du = 0.0f;
     b.dv = 0.0f;
+    b.inv = 0.5f;
   } else {
     const float pmax2 = fmaxf(px2, py2), pmin2 = fminf(px2, py2);
     int n = f.max_aniso;
@@ -94,6 +97,7 @@ __device__ __forceinline__ LodBase lod_base(const FilterArgs &f, float w0, float
     b.n = n;
     b.du = major_x ? d.x : d.z;
     b.dv = major_x ? d.y : d.w;
+    b.inv = 1.0f / (float)(n + 1);
   }
   return b;
 }
@@ -112,11 +116,13 @@ __device__ __forceinline__ LodSel lod_select(const FilterArgs &f, int k, const L
   s.n = b.n;
   s.du = b.du;
   s.dv = b.dv;
+  s.inv = b.inv;
   return s;
 }
 
-// Offset of anisotropic tap i (1..n) along the major axis, in units of it.
-__device__ __forceinline__ float aniso_offset(int i, int n) { return (float)i / (float)(n + 1) - 0.5f; }
+// Offset of anisotropic tap i (1..n) along the major axis, in units of it:
+// i / (n + 1) - 1/2, with inv = 1 / (n + 1) (monotonic in i).
+__device__ __forceinline__ float aniso_offset(int i, float inv) { return fmaf((float)i, inv, -0.5f); }
 
 // Filtered features of one level; smp(m, x, y) is the bilinear sample of mip
 // m at (x, y) as float3.
@@ -135,7 +141,7 @@ __device__ __forceinline__ float3 filter_level(const LodSel &s, float u, float v
   if (FILTER == 1) return tri(u, v);
   float3 acc = make_float3(0.f, 0.f, 0.f);
   for (int i = 1; i <= s.n; ++i) {
-    const float t = aniso_offset(i, s.n);
+    const float t = aniso_offset(i, s.inv);
     const float3 c = tri(fmaf(t, s.du, u), fmaf(t, s.dv, v));
     acc.x += c.x;
     acc.y += c.y;
@@ -167,6 +173,7 @@ __device__ __forceinline__ Tex16 trilinear16(const LodSel &s, float u, float v, 
 struct FiltStage {
   int m_lo[kMaxLevels];
   unsigned staged;
+  unsigned interior;  // bit r: every position of region r lies in [0, n - 2] on both axes
   int kbw[kRegions], kbase[kRegions];
 };
 
@@ -192,7 +199,7 @@ __device__ __forceinline__ FiltStage stage_footprints(const FilterArgs &f, const
     for (int k = 0; k < kMaxLevels; ++k) {
       if (k >= f.n_levels) break;
       const LodSel &s = sel[k];
-      const float ta = aniso_offset(1, s.n), tb = aniso_offset(s.n, s.n);
+      const float ta = aniso_offset(1, s.inv), tb = aniso_offset(s.n, s.inv);
       const float xa = tap_coord(fmaf(ta, s.du, u)), xb = tap_coord(fmaf(tb, s.du, u));
       const float ya = tap_coord(fmaf(ta, s.dv, v)), yb = tap_coord(fmaf(tb, s.dv, v));
       umin = fminf(umin, fminf(xa, xb));
@@ -218,7 +225,12 @@ __device__ __forceinline__ FiltStage stage_footprints(const FilterArgs &f, const
   const bool ay = q >= 2;
   const float dim = ay ? M.fh : M.fw;
   const float ext = q == 0 ? umin : (q == 1 ? umax : (q == 2 ? vmin : vmax));
-  const int ti = (int)tap_floor(ext, dim, (ay ? f.sy[k] : f.sx[k]) - 0.5f, dim - 2.0f);
+  const float cpos = (ay ? f.sy[k] : f.sx[k]) - 0.5f;
+  const int ti = (int)tap_floor(ext, dim, cpos, dim - 2.0f);
+  // the positions are monotonic in the coordinate: the extremes decide
+  const float raw = fmaf(ext, dim, cpos);
+  const unsigned long long outside =
+      __builtin_amdgcn_ballot_w64(lane < 4 * kRegions && !(raw >= 0.0f && raw <= dim - 2.0f));
   // every lane of quad r receives the four values of region r
   const int qbx = __builtin_amdgcn_mov_dpp(ti, 0x00, 0xF, 0xF, false);
   const int qex = __builtin_amdgcn_mov_dpp(ti, 0x55, 0xF, 0xF, false);
@@ -231,6 +243,10 @@ __device__ __forceinline__ FiltStage stage_footprints(const FilterArgs &f, const
   const int qitems = valid ? __mul24(qncol, qey - qby + 2) : 0;
   int kib[kRegions], total = 0;
   st.staged = 0u;
+  st.interior = 0u;
+#pragma unroll
+  for (int rr = 0; rr < kRegions; ++rr)
+    if (((outside >> (4 * rr)) & 0xFull) == 0) st.interior |= 1u << rr;
 #pragma unroll
   for (int rr = 0; rr < kRegions; ++rr) {
     const int items = __builtin_amdgcn_readlane(qitems, 4 * rr);
@@ -285,11 +301,21 @@ __device__ __forceinline__ FiltStage stage_footprints(const FilterArgs &f, const
 // Bilinear sample of a staged region: the taps of clamp_tap, four texels
 // from LDS, the FP16 blend (the same values sample_direct16 computes).
 __device__ __forceinline__ Tex16 staged_sample(const uint2 *stage, float fw, float fh, float cx, float cy,
-                                               int kbw, int kbase, float x, float y) {
+                                               int kbw, int kbase, float x, float y, bool interior) {
   int i0, j0;
   float fx, fy;
-  clamp_tap(tap_coord(x), fw, cx, fw - 2.0f, i0, fx);
-  clamp_tap(tap_coord(y), fh, cy, fh - 2.0f, j0, fy);
+  if (interior) {
+    // positions inside [0, n - 2]: floor and fraction as they stand, what
+    // clamp_tap gives there
+    const float px = fmaf(x, fw, cx), py = fmaf(y, fh, cy);
+    i0 = (int)px;
+    j0 = (int)py;
+    fx = __builtin_amdgcn_fractf(px);
+    fy = __builtin_amdgcn_fractf(py);
+  } else {
+    clamp_tap(tap_coord(x), fw, cx, fw - 2.0f, i0, fx);
+    clamp_tap(tap_coord(y), fh, cy, fh - 2.0f, j0, fy);
+  }
   const uint2 *t = stage + kbase + __mul24(j0, kbw) + i0;
   return lerp_tex16(tex16_from(t[0]), tex16_from(t[1]), tex16_from(t[kbw]), tex16_from(t[kbw + 1]), fx, fy);
 }
@@ -359,6 +385,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
         // this level's staged regions (the span's lowest mip m_lo and
         // m_lo + 1), as wave-uniform values
         const bool s0 = (st.staged >> (2 * k)) & 1u, s1 = (st.staged >> (2 * k + 1)) & 1u;
+        const bool in0 = (st.interior >> (2 * k)) & 1u, in1 = (st.interior >> (2 * k + 1)) & 1u;
         const int mlo = __builtin_amdgcn_readfirstlane(st.m_lo[k]);
         const MipArgs &M0 = f.mip[k][mlo];
         const MipArgs &M1 = f.mip[k][mlo + 1 < kMaxMips ? mlo + 1 : mlo];
@@ -371,7 +398,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
           if ((j == 0 && s0) || (j == 1 && s1)) {
             const bool one = j == 1;
             return staged_sample(stage, one ? M1.fw : M0.fw, one ? M1.fh : M0.fh, cx, cy, one ? kbw1 : kbw0,
-                                 one ? kb1 : kb0, x, y);
+                                 one ? kb1 : kb0, x, y, one ? in1 : in0);
           }
           return sample_direct16(mip_level(f, k, m), tap_coord(x), tap_coord(y), 0);
         };
