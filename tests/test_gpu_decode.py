@@ -85,7 +85,8 @@ def test_plain_f32_c1_all_pixels():
     assert np.all(err <= TOL_F32_REL * np.abs(ref))
 
 
-@pytest.mark.parametrize("compute,tol", [("f16", TOL_F16_ABS), ("bf16", TOL_BF16_ABS), ("f32", None)])
+@pytest.mark.parametrize("compute,tol", [("f16", TOL_F16_ABS), ("bf16", TOL_BF16_ABS), ("f32", None),
+                                         ("fp8", TOL_FP8_ABS)])
 def test_c1_shape_variants(compute, tol):
     """Random biases, ragged sizes, wrap addressing, no shift, uv outside [0,1],
     fewer levels, 9 output channels."""
@@ -106,7 +107,11 @@ def test_c1_shape_variants(compute, tol):
         Ws, bs = I.xavier_mlp(rng, c["dims"], bias="normal")
         uv = (rng.random((c["n"], 2)) * (c["uvr"][1] - c["uvr"][0]) + c["uvr"][0]).astype(np.float32)
         lat, mlp = _gpu_case(lat_np, Ws, bs, c["shift"], c["address"])
-        out = ntc.decode(lat, mlp, torch.from_numpy(uv).cuda(), compute=compute).cpu().numpy()
+        packed = None
+        if compute == "fp8":
+            # ranges calibrated on the decoded coordinates themselves
+            packed = ntc.pack(mlp, "fp8", act_amax=ntc.calibrate_fp8(lat, mlp, torch.from_numpy(uv).cuda()))
+        out = ntc.decode(lat, mlp, torch.from_numpy(uv).cuda(), compute=compute, packed=packed).cpu().numpy()
         olat, omlp = _oracle_case(lat_np, Ws, bs, c["shift"], c["address"])
         ref = O.decode(olat, omlp, uv)
         err = _report(f"variant {ci} {compute}", out, ref)
