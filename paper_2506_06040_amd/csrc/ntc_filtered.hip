@@ -29,6 +29,12 @@ namespace {
 
 constexpr int kFiltStageTexels = 2048;  // LDS texels (8 bytes each) per wavefront
 constexpr int kRegions = 2 * kMaxLevels;
+#ifndef NTC_FILT_TRI_SUBS  // 64-pixel sub-spans per staged span of the trilinear decode
+#define NTC_FILT_TRI_SUBS 16
+#endif
+#ifndef NTC_FILT_ANI_SUBS  // and of the anisotropic decode
+#define NTC_FILT_ANI_SUBS 4
+#endif
 
 // Mip m of level k as a sampling table entry (clamp to edge).
 __device__ __forceinline__ TabLevel mip_level(const FilterArgs &f, int k, int m) {
@@ -102,12 +108,18 @@ __device__ __forceinline__ LodBase lod_base(const FilterArgs &f, float w0, float
   return b;
 }
 
+// Level of detail of level k clamped to its mip range, from a base whose
+// level of detail is `shift` above this level's (NaN and -inf give 0).
+__device__ __forceinline__ float clamped_lod(const FilterArgs &f, int k, float lod, float shift) {
+  return fminf(fmaxf(lod - shift, 0.0f), (float)(f.n_mips[k] - 1));
+}
+
 // Selection on level k from a base whose level of detail is `shift` above
 // this level's.
 __device__ __forceinline__ LodSel lod_select(const FilterArgs &f, int k, const LodBase &b, float shift) {
   LodSel s;
   const int nm = f.n_mips[k];
-  const float lod = fminf(fmaxf(b.lod - shift, 0.0f), (float)(nm - 1));  // NaN and -inf give 0
+  const float lod = clamped_lod(f, k, b.lod, shift);
   int m0 = (int)floorf(lod);
   m0 = m0 < 0 ? 0 : (m0 > nm - 1 ? nm - 1 : m0);
   const float t = lod - (float)m0;
@@ -177,54 +189,70 @@ struct FiltStage {
   int kbw[kRegions], kbase[kRegions];
 };
 
-__device__ __forceinline__ int wave_min_i(int v) {
-  const int r = row_min_i(v);
-  const int a = __builtin_amdgcn_readlane(r, 0), b = __builtin_amdgcn_readlane(r, 16);
-  const int c = __builtin_amdgcn_readlane(r, 32), d = __builtin_amdgcn_readlane(r, 48);
-  return min(min(a, b), min(c, d));
+// Wave-uniform footprint of a span: the extreme coordinates of every
+// position of every used level, per level the lowest first mip m_lo and
+// whether some sample reads mip m_lo + 1 (bit k of need_hi).
+struct SpanFoot {
+  float umin, umax, vmin, vmax;
+  int m_lo[kMaxLevels];
+  unsigned need_hi;
+};
+
+// Extreme coordinates of one pixel's positions: the pixel itself and, for
+// anisotropic filtering, its first and last tap along the major axis (the
+// taps are monotonic in i).
+template <int FILTER>
+__device__ __forceinline__ void extend_taps(const LodBase &b, float u, float v, float &umin, float &umax, float &vmin,
+                                            float &vmax) {
+  const float uc = tap_coord(u), vc = tap_coord(v);
+  umin = fminf(umin, uc);
+  umax = fmaxf(umax, uc);
+  vmin = fminf(vmin, vc);
+  vmax = fmaxf(vmax, vc);
+  if (FILTER != 1) {
+    const float ta = aniso_offset(1, b.inv), tb = aniso_offset(b.n, b.inv);
+    const float xa = tap_coord(fmaf(ta, b.du, u)), xb = tap_coord(fmaf(tb, b.du, u));
+    const float ya = tap_coord(fmaf(ta, b.dv, v)), yb = tap_coord(fmaf(tb, b.dv, v));
+    umin = fminf(umin, fminf(xa, xb));
+    umax = fmaxf(umax, fmaxf(xa, xb));
+    vmin = fminf(vmin, fminf(ya, yb));
+    vmax = fmaxf(vmax, fmaxf(ya, yb));
+  }
 }
 
-// Footprints of the span and their staging. sel: this lane's selections,
-// (u, v) its pixel; stage: kFiltStageTexels texels; srec: 2 kRegions
-// records. Regions are taken in order while they fit.
-template <int FILTER>
-__device__ __forceinline__ FiltStage stage_footprints(const FilterArgs &f, const LodSel (&sel)[kMaxLevels], float u,
-                                                      float v, uint2 *stage, f32x4 *srec, int salt) {
+// Mip range of level k over a span from the extremes of its clamped level
+// of detail: floor and ceiling are monotonic, so the lowest first mip is the
+// floor of the minimum and the highest mip read (m0, or m0 + 1 when t > 0)
+// the ceiling of the maximum.
+__device__ __forceinline__ void mip_range(const FilterArgs &f, int k, float lo, float hi, SpanFoot &ft) {
+  const int nm = f.n_mips[k];
+  int m = (int)floorf(lo);
+  m = m < 0 ? 0 : (m > nm - 1 ? nm - 1 : m);
+  ft.m_lo[k] = m;
+  if ((int)ceilf(hi) > m) ft.need_hi |= 1u << k;
+}
+
+// Staging of the span's regions. stage: kFiltStageTexels texels; srec:
+// 2 kRegions records. Regions are taken in order while they fit; a region of
+// mip m_lo + 1 that no sample reads is left out.
+__device__ __forceinline__ FiltStage stage_footprints(const FilterArgs &f, const SpanFoot &ft, uint2 *stage,
+                                                      f32x4 *srec, int salt) {
   const int lane = threadIdx.x & 63;
   FiltStage st;
-  // extreme coordinates of every position of every used level of this pixel
-  float umin = tap_coord(u), umax = umin, vmin = tap_coord(v), vmax = vmin;
-  if (FILTER != 1) {
 #pragma unroll
-    for (int k = 0; k < kMaxLevels; ++k) {
-      if (k >= f.n_levels) break;
-      const LodSel &s = sel[k];
-      const float ta = aniso_offset(1, s.inv), tb = aniso_offset(s.n, s.inv);
-      const float xa = tap_coord(fmaf(ta, s.du, u)), xb = tap_coord(fmaf(tb, s.du, u));
-      const float ya = tap_coord(fmaf(ta, s.dv, v)), yb = tap_coord(fmaf(tb, s.dv, v));
-      umin = fminf(umin, fminf(xa, xb));
-      umax = fmaxf(umax, fmaxf(xa, xb));
-      vmin = fminf(vmin, fminf(ya, yb));
-      vmax = fmaxf(vmax, fmaxf(ya, yb));
-    }
-  }
-  umin = wave_min_key(umin);
-  umax = wave_max_key(umax);
-  vmin = wave_min_key(vmin);
-  vmax = wave_max_key(vmax);
-#pragma unroll
-  for (int k = 0; k < kMaxLevels; ++k) st.m_lo[k] = k < f.n_levels ? wave_min_i(sel[k].m0) : 0;
+  for (int k = 0; k < kMaxLevels; ++k) st.m_lo[k] = ft.m_lo[k];
   // lane 4 r + q (r < kRegions): tap index of an extreme coordinate on
   // region r; q = 0: left tap of umin, 1: left tap of umax, 2: top tap of
   // vmin, 3: top tap of vmax
   const int r = (lane >> 2) & (kRegions - 1), q = lane & 3, k = r >> 1;
-  const int mlo = k == 0 ? st.m_lo[0] : (k == 1 ? st.m_lo[1] : (k == 2 ? st.m_lo[2] : st.m_lo[3]));
+  const int mlo = k == 0 ? ft.m_lo[0] : (k == 1 ? ft.m_lo[1] : (k == 2 ? ft.m_lo[2] : ft.m_lo[3]));
   const int m = mlo + (r & 1);
-  const bool valid = lane < 4 * kRegions && k < f.n_levels && m < f.n_mips[k];
+  const bool valid = lane < 4 * kRegions && k < f.n_levels && m < f.n_mips[k] &&
+                     ((r & 1) == 0 || ((ft.need_hi >> k) & 1u));
   const MipArgs &M = f.mip[k][valid ? m : 0];
   const bool ay = q >= 2;
   const float dim = ay ? M.fh : M.fw;
-  const float ext = q == 0 ? umin : (q == 1 ? umax : (q == 2 ? vmin : vmax));
+  const float ext = q == 0 ? ft.umin : (q == 1 ? ft.umax : (q == 2 ? ft.vmin : ft.vmax));
   const float cpos = (ay ? f.sy[k] : f.sx[k]) - 0.5f;
   const int ti = (int)tap_floor(ext, dim, cpos, dim - 2.0f);
   // the positions are monotonic in the coordinate: the extremes decide
@@ -320,7 +348,13 @@ __device__ __forceinline__ Tex16 staged_sample(const uint2 *stage, float fw, flo
   return lerp_tex16(tex16_from(t[0]), tex16_from(t[1]), tex16_from(t[kbw]), tex16_from(t[kbw + 1]), fx, fy);
 }
 
-template <class P, int HID, int NL, int VEC4, int FILTER>
+// A span is SUBS sub-spans of 64 consecutive pixels: the footprints of all
+// its pixels are staged once, then each sub-span is sampled and run through
+// the MLP. Long spans spread the footprint reductions, the staging records
+// and the partly filled staging passes over more pixels; trilinear spans
+// take 1024 pixels, anisotropic ones (footprints stretched along the major
+// axis) 256.
+template <class P, int HID, int NL, int VEC4, int FILTER, int SUBS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PER_SIMD, NTC_WAVES_PER_SIMD))) void decode_filtered_kernel(FilterArgs f) {
   extern __shared__ f32x4 smem[];
   const DecodeArgs &a = f.d;
@@ -333,110 +367,204 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
   BiasLds<HID, NL>::fill(bias, a.packed, a.lay, lane);
   W.ready();
   __syncthreads();
-  const int64_t n_sub = (a.n + 63) / 64;
-  // this lane's pixel of span s (lanes past the end repeat the last pixel)
-  auto pixel_of = [&](int64_t s) {
-    const int64_t left = a.n - s * 64;
-    return s * 64 + (lane < left ? lane : left - 1);
+  constexpr int kSpanPx = 64 * SUBS;
+  const int64_t n_span = (a.n + kSpanPx - 1) / kSpanPx;
+  // this lane's pixel of sub-span i of span s (pixels past the end repeat
+  // the last one)
+  auto pixel_of = [&](int64_t s, int i) {
+    const int64_t p = s * kSpanPx + 64 * i + lane;
+    return p < a.n ? p : a.n - 1;
   };
-  // uv and derivatives are loaded one span ahead
+  // One-sub-span spans load their uv and derivatives one span ahead; longer
+  // spans load theirs when they start (registers held through the MLP would
+  // spill; the other wavefront of the SIMD works while the loads are in
+  // flight).
   float2 uv_next = make_float2(0.f, 0.f);
   float4 d_next = make_float4(0.f, 0.f, 0.f, 0.f);
-  if ((int64_t)blockIdx.x < n_sub) {
-    const int64_t p = pixel_of(blockIdx.x);
+  if (SUBS == 1 && (int64_t)blockIdx.x < n_span) {
+    const int64_t p = pixel_of(blockIdx.x, 0);
     uv_next = a.uv[p];
     d_next = f.duv[p];
   }
-  for (int64_t s = blockIdx.x; s < n_sub; s += gridDim.x) {
-    const int64_t first = s * 64;
-    const int64_t left = a.n - first;
-    const float2 uv = uv_next;
-    const float4 d = d_next;
-    if (s + gridDim.x < n_sub) {
-      const int64_t p = pixel_of(s + gridDim.x);
-      uv_next = a.uv[p];
-      d_next = f.duv[p];
-    }
-    LodSel sel[kMaxLevels];
-    if (f.shared_lod) {
-      const LodBase b = lod_base<FILTER>(f, f.w0[0], f.h0[0], d);
-#pragma unroll
-      for (int k = 0; k < kMaxLevels; ++k) sel[k] = lod_select(f, k < f.n_levels ? k : 0, b, f.lod_shift[k]);
+  for (int64_t s = blockIdx.x; s < n_span; s += gridDim.x) {
+    float2 uv[SUBS];
+    float4 d[SUBS];
+    if constexpr (SUBS == 1) {
+      uv[0] = uv_next;
+      d[0] = d_next;
+      if (s + gridDim.x < n_span) {
+        const int64_t p = pixel_of(s + gridDim.x, 0);
+        uv_next = a.uv[p];
+        d_next = f.duv[p];
+      }
     } else {
+#pragma unroll
+      for (int i = 0; i < SUBS; ++i) {
+        const int64_t p = pixel_of(s, i);
+        uv[i] = a.uv[p];
+        d[i] = f.duv[p];
+      }
+    }
+    // footprint of the span: per lane over its pixels, then over the wave
+    float umin = __builtin_inff(), umax = -__builtin_inff(), vmin = __builtin_inff(), vmax = -__builtin_inff();
+    SpanFoot ft;
+    ft.need_hi = 0u;
+    LodBase bs[SUBS];  // shared level of detail: the base of each pixel
+    if (f.shared_lod) {
+      // every level's clamped level of detail is monotonic in the base's
+      float blo = __builtin_inff(), bhi = -__builtin_inff();
+#pragma unroll
+      for (int i = 0; i < SUBS; ++i) {
+        bs[i] = lod_base<FILTER>(f, f.w0[0], f.h0[0], d[i]);
+        const float l = fmaxf(bs[i].lod, -__builtin_inff());  // NaN as -inf: both clamp to 0
+        blo = fminf(blo, l);
+        bhi = fmaxf(bhi, l);
+        extend_taps<FILTER>(bs[i], uv[i].x, uv[i].y, umin, umax, vmin, vmax);
+      }
+      blo = wave_min_key(blo);
+      bhi = wave_max_key(bhi);
 #pragma unroll
       for (int k = 0; k < kMaxLevels; ++k) {
-        const int kk = k < f.n_levels ? k : 0;
-        sel[k] = lod_select(f, kk, lod_base<FILTER>(f, f.w0[kk], f.h0[kk], d), 0.0f);
+        ft.m_lo[k] = 0;
+        if (k < f.n_levels)
+          mip_range(f, k, clamped_lod(f, k, blo, f.lod_shift[k]), clamped_lod(f, k, bhi, f.lod_shift[k]), ft);
       }
-    }
-    const FiltStage st = stage_footprints<FILTER>(f, sel, uv.x, uv.y, stage, srec, (int)s);
-    typename P::Frag bx[2];
-    Tex16 c16[kMaxLevels];
-    float xl[8], xh[8];
-#pragma unroll
-    for (int k = 0; k < kMaxLevels; ++k) {
-      // levels past n_levels: zero features (their (b, 1) pads keep the
-      // constant 1 of the bias slots)
-      const half2_t z = {(_Float16)0.0f, (_Float16)0.0f}, z1 = {(_Float16)0.0f, (_Float16)1.0f};
-      c16[k].rg = z;
-      c16[k].b1 = z1;
-      float3 c = make_float3(0.f, 0.f, 0.f);
-      if (k < f.n_levels) {
-        // this level's staged regions (the span's lowest mip m_lo and
-        // m_lo + 1), as wave-uniform values
-        const bool s0 = (st.staged >> (2 * k)) & 1u, s1 = (st.staged >> (2 * k + 1)) & 1u;
-        const bool in0 = (st.interior >> (2 * k)) & 1u, in1 = (st.interior >> (2 * k + 1)) & 1u;
-        const int mlo = __builtin_amdgcn_readfirstlane(st.m_lo[k]);
-        const MipArgs &M0 = f.mip[k][mlo];
-        const MipArgs &M1 = f.mip[k][mlo + 1 < kMaxMips ? mlo + 1 : mlo];
-        const float cx = f.sx[k] - 0.5f, cy = f.sy[k] - 0.5f;
-        const int kbw0 = st.kbw[2 * k], kbw1 = st.kbw[2 * k + 1];
-        const int kb0 = st.kbase[2 * k], kb1 = st.kbase[2 * k + 1];
-        // sample of mip m at (x, y): from a staged region or fetched directly
-        auto smp = [&](int m, float x, float y) -> Tex16 {
-          const int j = m - mlo;
-          if ((j == 0 && s0) || (j == 1 && s1)) {
-            const bool one = j == 1;
-            return staged_sample(stage, one ? M1.fw : M0.fw, one ? M1.fh : M0.fh, cx, cy, one ? kbw1 : kbw0,
-                                 one ? kb1 : kb0, x, y, one ? in1 : in0);
-          }
-          return sample_direct16(mip_level(f, k, m), tap_coord(x), tap_coord(y), 0);
-        };
-        if constexpr (FILTER == 1)
-          c16[k] = trilinear16(sel[k], uv.x, uv.y, smp);
-        else
-          c = filter_level<FILTER>(sel[k], uv.x, uv.y, [&](int m, float x, float y) { return tex_f3(smp(m, x, y)); });
-      }
-      if constexpr (FILTER != 1) put_level(xl, xh, k, c);
-    }
-    if constexpr (FILTER == 1) {
-      // trilinear: FP16 samples blended in packed FP16 straight into the
-      // first layer's operands
-      operands16(c16, uv.x, uv.y, bx);
     } else {
-      pixel_operands<P>(xl, xh, uv.x, uv.y, W.in_scale, bx);
+      float lo[kMaxLevels], hi[kMaxLevels];
+#pragma unroll
+      for (int k = 0; k < kMaxLevels; ++k) {
+        lo[k] = __builtin_inff();
+        hi[k] = -__builtin_inff();
+      }
+#pragma unroll
+      for (int i = 0; i < SUBS; ++i) {
+#pragma unroll
+        for (int k = 0; k < kMaxLevels; ++k) {
+          const int kk = k < f.n_levels ? k : 0;
+          const LodBase b = lod_base<FILTER>(f, f.w0[kk], f.h0[kk], d[i]);
+          const float l = clamped_lod(f, kk, b.lod, 0.0f);
+          lo[k] = fminf(lo[k], l);
+          hi[k] = fmaxf(hi[k], l);
+          extend_taps<FILTER>(b, uv[i].x, uv[i].y, umin, umax, vmin, vmax);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kMaxLevels; ++k) {
+        ft.m_lo[k] = 0;
+        if (k < f.n_levels) mip_range(f, k, wave_min_key(lo[k]), wave_max_key(hi[k]), ft);
+      }
     }
-    const int span = left < 64 ? (int)left : 64;
-    // ReLU by the [0, 1] clamp of the conversion when the image is scaled
-    // for it and every coordinate of the span lies in the unit square (the
-    // features are then blends of latent values in [0, 1], as in the
-    // unfiltered decode)
-    const bool in_unit =
-        __builtin_amdgcn_ballot_w64(!(uv.x >= 0.0f && uv.x <= 1.0f && uv.y >= 0.0f && uv.y <= 1.0f)) == 0;
-    if (in_unit && W.unit_relu != 0)
-      subspan_mlp<P, HID, NL, VEC4, true>(a, W, bias, span_out(a, first, span), bx, 0, (int)first);
-    else
-      subspan_mlp<P, HID, NL, VEC4, false>(a, W, bias, span_out(a, first, span), bx, 0, (int)first);
+    ft.umin = wave_min_key(umin);
+    ft.umax = wave_max_key(umax);
+    ft.vmin = wave_min_key(vmin);
+    ft.vmax = wave_max_key(vmax);
+    // staged once for all the span's sub-spans (regions that do not fit are
+    // fetched directly, which costs less than staging each sub-span on its
+    // own)
+    const FiltStage st = stage_footprints(f, ft, stage, srec, (int)s);
+    // one sub-span per iteration (not unrolled: the code of a sub-span is
+    // large). The uv and derivatives of sub-span i + 1 are loaded again
+    // (from the cache) while sub-span i runs, so that no per-pixel array is
+    // held through the MLP; the trilinear level of detail is recomputed, the
+    // anisotropic base (with its tap count) moves to the front of bs.
+    float2 uvc = uv[0];
+    float4 dc = d[0];
+#pragma unroll 1
+    for (int i = 0; i < SUBS; ++i) {
+      const int64_t first = s * kSpanPx + 64 * i;
+      if (first >= a.n) break;
+      const int64_t left = a.n - first;
+      const float u = uvc.x, v = uvc.y;
+      const float4 di = dc;
+      if (SUBS > 1 && i + 1 < SUBS) {
+        const int64_t p = pixel_of(s, i + 1);
+        uvc = a.uv[p];
+        dc = f.duv[p];
+      }
+      LodSel sel[kMaxLevels];
+      if (f.shared_lod) {
+        const LodBase b = FILTER == 1 ? lod_base<FILTER>(f, f.w0[0], f.h0[0], di) : bs[0];
+#pragma unroll
+        for (int k = 0; k < kMaxLevels; ++k) sel[k] = lod_select(f, k < f.n_levels ? k : 0, b, f.lod_shift[k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < kMaxLevels; ++k) {
+          const int kk = k < f.n_levels ? k : 0;
+          sel[k] = lod_select(f, kk, lod_base<FILTER>(f, f.w0[kk], f.h0[kk], di), 0.0f);
+        }
+      }
+      if constexpr (FILTER != 1) {
+#pragma unroll
+        for (int j = 0; j + 1 < SUBS; ++j) bs[j] = bs[j + 1];
+      }
+      typename P::Frag bx[2];
+      Tex16 c16[kMaxLevels];
+      float xl[8], xh[8];
+#pragma unroll
+      for (int k = 0; k < kMaxLevels; ++k) {
+        // levels past n_levels: zero features (their (b, 1) pads keep the
+        // constant 1 of the bias slots)
+        const half2_t z = {(_Float16)0.0f, (_Float16)0.0f}, z1 = {(_Float16)0.0f, (_Float16)1.0f};
+        c16[k].rg = z;
+        c16[k].b1 = z1;
+        float3 c = make_float3(0.f, 0.f, 0.f);
+        if (k < f.n_levels) {
+          // this level's staged regions (the span's lowest mip m_lo and
+          // m_lo + 1), as wave-uniform values
+          const bool s0 = (st.staged >> (2 * k)) & 1u, s1 = (st.staged >> (2 * k + 1)) & 1u;
+          const bool in0 = (st.interior >> (2 * k)) & 1u, in1 = (st.interior >> (2 * k + 1)) & 1u;
+          const int mlo = __builtin_amdgcn_readfirstlane(st.m_lo[k]);
+          const MipArgs &M0 = f.mip[k][mlo];
+          const MipArgs &M1 = f.mip[k][mlo + 1 < kMaxMips ? mlo + 1 : mlo];
+          const float cx = f.sx[k] - 0.5f, cy = f.sy[k] - 0.5f;
+          const int kbw0 = st.kbw[2 * k], kbw1 = st.kbw[2 * k + 1];
+          const int kb0 = st.kbase[2 * k], kb1 = st.kbase[2 * k + 1];
+          // sample of mip m at (x, y): from a staged region or fetched directly
+          auto smp = [&](int m, float x, float y) -> Tex16 {
+            const int j = m - mlo;
+            if ((j == 0 && s0) || (j == 1 && s1)) {
+              const bool one = j == 1;
+              return staged_sample(stage, one ? M1.fw : M0.fw, one ? M1.fh : M0.fh, cx, cy, one ? kbw1 : kbw0,
+                                   one ? kb1 : kb0, x, y, one ? in1 : in0);
+            }
+            return sample_direct16(mip_level(f, k, m), tap_coord(x), tap_coord(y), 0);
+          };
+          if constexpr (FILTER == 1)
+            c16[k] = trilinear16(sel[k], u, v, smp);
+          else
+            c = filter_level<FILTER>(sel[k], u, v, [&](int m, float x, float y) { return tex_f3(smp(m, x, y)); });
+        }
+        if constexpr (FILTER != 1) put_level(xl, xh, k, c);
+      }
+      if constexpr (FILTER == 1) {
+        // trilinear: FP16 samples blended in packed FP16 straight into the
+        // first layer's operands
+        operands16(c16, u, v, bx);
+      } else {
+        pixel_operands<P>(xl, xh, u, v, W.in_scale, bx);
+      }
+      const int span = left < 64 ? (int)left : 64;
+      // ReLU by the [0, 1] clamp of the conversion when the image is scaled
+      // for it and every coordinate of the sub-span lies in the unit square
+      // (the features are then blends of latent values in [0, 1], as in the
+      // unfiltered decode)
+      const bool in_unit = __builtin_amdgcn_ballot_w64(!(u >= 0.0f && u <= 1.0f && v >= 0.0f && v <= 1.0f)) == 0;
+      if (in_unit && W.unit_relu != 0)
+        subspan_mlp<P, HID, NL, VEC4, true>(a, W, bias, span_out(a, first, span), bx, 0, (int)first);
+      else
+        subspan_mlp<P, HID, NL, VEC4, false>(a, W, bias, span_out(a, first, span), bx, 0, (int)first);
+    }
   }
 }
 
 template <int HID, int VEC4, int FILTER>
 hipError_t launch_nl(const FilterArgs &f, int n_layers, int grid, hipStream_t st) {
+  constexpr int S = FILTER == 1 ? NTC_FILT_TRI_SUBS : NTC_FILT_ANI_SUBS;
   const size_t lds = (size_t)(BiasLds<HID, 5>::kCount + 2 * kRegions) * sizeof(f32x4) + kFiltStageTexels * sizeof(uint2);
   switch (n_layers) {
-    case 2: hipLaunchKernelGGL((decode_filtered_kernel<PrecF16, HID, 2, VEC4, FILTER>), dim3(grid), dim3(64), lds, st, f); break;
-    case 3: hipLaunchKernelGGL((decode_filtered_kernel<PrecF16, HID, 3, VEC4, FILTER>), dim3(grid), dim3(64), lds, st, f); break;
-    case 4: hipLaunchKernelGGL((decode_filtered_kernel<PrecF16, HID, 4, VEC4, FILTER>), dim3(grid), dim3(64), lds, st, f); break;
+    case 2: hipLaunchKernelGGL((decode_filtered_kernel<PrecF16, HID, 2, VEC4, FILTER, S>), dim3(grid), dim3(64), lds, st, f); break;
+    case 3: hipLaunchKernelGGL((decode_filtered_kernel<PrecF16, HID, 3, VEC4, FILTER, S>), dim3(grid), dim3(64), lds, st, f); break;
+    case 4: hipLaunchKernelGGL((decode_filtered_kernel<PrecF16, HID, 4, VEC4, FILTER, S>), dim3(grid), dim3(64), lds, st, f); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -460,8 +588,9 @@ hipError_t launch_vec(const FilterArgs &f, int n_layers, int grid, hipStream_t s
 
 hipError_t launch_decode_filtered(const FilterArgs &f, const MlpShape &s, int grid_waves, hipStream_t st) {
   int64_t grid = grid_waves;
-  const int64_t n_sub = (f.d.n + 63) / 64;
-  if (grid > n_sub) grid = n_sub;
+  const int64_t span_px = 64 * (f.filter == 1 ? NTC_FILT_TRI_SUBS : NTC_FILT_ANI_SUBS);
+  const int64_t n_span = (f.d.n + span_px - 1) / span_px;
+  if (grid > n_span) grid = n_span;
   if (grid < 1) grid = 1;
   switch (s.hid) {
     case 16: return launch_vec<16>(f, s.n_layers, (int)grid, st);

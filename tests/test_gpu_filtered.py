@@ -158,3 +158,27 @@ def test_unrelated_level_sizes(filt):
     print(f"[unrelated sizes {filt}] left out {int((~keep).sum())} max err {err:.2e}", flush=True)
     assert (~keep).sum() <= 1e-3 * n
     assert err <= TOL_F16_ABS
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 255, 257, 1023, 1025, 2049])
+def test_ragged_span_lengths(n):
+    """Pixel counts around the 64-pixel sub-spans and the 256- and
+    1024-pixel staged spans: the last span is partly filled, its missing
+    pixels repeat the last one and are never stored."""
+    ntc = _ntc()
+    sizes = [(128, 128), (64, 64), (32, 32), (16, 16)]
+    rng, chains, Ws, bs = _case(7, sizes)
+    uv, duv = I.perspective_plane(64, 48, far=12.0)
+    sel = rng.choice(uv.shape[0], size=n, replace=n > uv.shape[0])
+    uv, duv = np.ascontiguousarray(uv[sel]), np.ascontiguousarray(duv[sel] * np.float32(2.0))
+    lm, mlp = ntc.LatentMips(chains, shift=I.PAPER_SHIFT), ntc.Mlp(Ws, bs)
+    for filt in ("trilinear", "anisotropic"):
+        out = torch.full((n + 7, 8), -7.0, device="cuda")
+        ntc.decode_filtered(lm, mlp, torch.from_numpy(uv).cuda(), torch.from_numpy(duv).cuda(), filter=filt,
+                            max_aniso=8, out=out[:n])
+        got = out.cpu().numpy()
+        assert np.all(got[n:] == -7.0), filt  # nothing written past the end
+        ref = F.decode(chains, I.PAPER_SHIFT, O.Mlp(Ws, bs), uv, duv, filt, 8)
+        keep = ~_ambiguous(sizes, duv, 8) if filt == "anisotropic" else np.ones(n, bool)
+        err = np.abs(got[:n] - ref)[keep].max() if keep.any() else 0.0
+        assert err <= TOL_F16_ABS, (filt, n, err)
