@@ -53,6 +53,10 @@ __device__ __forceinline__ TabLevel mip_level(const FilterArgs &f, int k, int m)
   return L;
 }
 
+__device__ __forceinline__ float uniform_f(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
 __device__ __forceinline__ float3 tex_f3(Tex16 c) {
   return make_float3((float)c.rg[0], (float)c.rg[1], (float)c.b1[0]);
 }
@@ -125,6 +129,25 @@ __device__ __forceinline__ LodSel lod_select(const FilterArgs &f, int k, const L
   const float t = lod - (float)m0;
   s.m0 = m0;
   s.t = (t > 0.0f && m0 + 1 < nm) ? t : 0.0f;
+  s.n = b.n;
+  s.du = b.du;
+  s.dv = b.dv;
+  s.inv = b.inv;
+  return s;
+}
+
+// The same selection when the base's level of detail is a non-negative
+// integer e above this level's, from the floor fl and fraction fr of the
+// base's (clamped to [-64, 64], NaN to -64): where the level's value
+// lod - e is not clamped it is exact, so its floor is fl - e and its
+// fraction fr; where it is, the first or the last mip is taken alone.
+__device__ __forceinline__ LodSel lod_select_int(const FilterArgs &f, int k, const LodBase &b, int fl, float fr,
+                                                 int e) {
+  LodSel s;
+  const int nm = f.n_mips[k];
+  const int m = fl - e;
+  s.m0 = m < 0 ? 0 : (m > nm - 1 ? nm - 1 : m);
+  s.t = (m >= 0 && m < nm - 1) ? fr : 0.0f;
   s.n = b.n;
   s.du = b.du;
   s.dv = b.dv;
@@ -369,6 +392,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
   __syncthreads();
   constexpr int kSpanPx = 64 * SUBS;
   const int64_t n_span = (a.n + kSpanPx - 1) / kSpanPx;
+  // shared level of detail with every level at or below level 0's size
+  bool int_shift = f.shared_lod != 0;
+#pragma unroll
+  for (int k = 0; k < kMaxLevels; ++k)
+    if (k < f.n_levels && f.lod_shift[k] < 0.0f) int_shift = false;
   // this lane's pixel of sub-span i of span s (pixels past the end repeat
   // the last one)
   auto pixel_of = [&](int64_t s, int i) {
@@ -484,8 +512,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
       LodSel sel[kMaxLevels];
       if (f.shared_lod) {
         const LodBase b = FILTER == 1 ? lod_base<FILTER>(f, f.w0[0], f.h0[0], di) : bs[0];
+        if (int_shift) {
+          const float l = fminf(fmaxf(b.lod, -64.0f), 64.0f);
+          const float fl = floorf(l);
+          const float fr = l - fl;
 #pragma unroll
-        for (int k = 0; k < kMaxLevels; ++k) sel[k] = lod_select(f, k < f.n_levels ? k : 0, b, f.lod_shift[k]);
+          for (int k = 0; k < kMaxLevels; ++k)
+            sel[k] = lod_select_int(f, k < f.n_levels ? k : 0, b, (int)fl, fr, (int)f.lod_shift[k]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < kMaxLevels; ++k) sel[k] = lod_select(f, k < f.n_levels ? k : 0, b, f.lod_shift[k]);
+        }
       } else {
 #pragma unroll
         for (int k = 0; k < kMaxLevels; ++k) {
@@ -514,8 +551,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
           const bool s0 = (st.staged >> (2 * k)) & 1u, s1 = (st.staged >> (2 * k + 1)) & 1u;
           const bool in0 = (st.interior >> (2 * k)) & 1u, in1 = (st.interior >> (2 * k + 1)) & 1u;
           const int mlo = __builtin_amdgcn_readfirstlane(st.m_lo[k]);
+          // sizes of the two staged mips as wave-uniform values (a per-lane
+          // choice between their addresses would load them per lane)
           const MipArgs &M0 = f.mip[k][mlo];
           const MipArgs &M1 = f.mip[k][mlo + 1 < kMaxMips ? mlo + 1 : mlo];
+          const float fw0 = uniform_f(M0.fw), fh0 = uniform_f(M0.fh);
+          const float fw1 = uniform_f(M1.fw), fh1 = uniform_f(M1.fh);
           const float cx = f.sx[k] - 0.5f, cy = f.sy[k] - 0.5f;
           const int kbw0 = st.kbw[2 * k], kbw1 = st.kbw[2 * k + 1];
           const int kb0 = st.kbase[2 * k], kb1 = st.kbase[2 * k + 1];
@@ -524,7 +565,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
             const int j = m - mlo;
             if ((j == 0 && s0) || (j == 1 && s1)) {
               const bool one = j == 1;
-              return staged_sample(stage, one ? M1.fw : M0.fw, one ? M1.fh : M0.fh, cx, cy, one ? kbw1 : kbw0,
+              return staged_sample(stage, one ? fw1 : fw0, one ? fh1 : fh0, cx, cy, one ? kbw1 : kbw0,
                                    one ? kb1 : kb0, x, y, one ? in1 : in0);
             }
             return sample_direct16(mip_level(f, k, m), tap_coord(x), tap_coord(y), 0);
