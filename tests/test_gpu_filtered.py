@@ -182,3 +182,24 @@ def test_ragged_span_lengths(n):
         keep = ~_ambiguous(sizes, duv, 8) if filt == "anisotropic" else np.ones(n, bool)
         err = np.abs(got[:n] - ref)[keep].max() if keep.any() else 0.0
         assert err <= TOL_F16_ABS, (filt, n, err)
+
+
+@pytest.mark.parametrize("filt", ["trilinear", "anisotropic"])
+def test_level_larger_than_level0(filt):
+    """Power-of-two levels where level 1 is twice level 0's size: the level
+    of detail is still shared (shift -1 for level 1) but not every shift is
+    a non-negative integer, so the selection takes the general form."""
+    ntc = _ntc()
+    sizes = [(64, 64), (128, 128), (32, 32), (16, 16)]
+    rng, chains, Ws, bs = _case(8, sizes)
+    uv, duv = I.perspective_plane(96, 64, far=16.0)
+    duv = duv * np.float32(3.0)
+    out = ntc.decode_filtered(ntc.LatentMips(chains, shift=I.PAPER_SHIFT), ntc.Mlp(Ws, bs),
+                              torch.from_numpy(uv).cuda(), torch.from_numpy(duv).cuda(), filter=filt,
+                              max_aniso=8).cpu().numpy()
+    ref = F.decode(chains, I.PAPER_SHIFT, O.Mlp(Ws, bs), uv, duv, filt, 8)
+    keep = ~_ambiguous(sizes, duv, 8) if filt == "anisotropic" else np.ones(uv.shape[0], bool)
+    err = np.abs(out - ref)[keep].max()
+    print(f"[larger level 1 {filt}] left out {int((~keep).sum())} max err {err:.2e}", flush=True)
+    assert (~keep).sum() <= 1e-3 * uv.shape[0]
+    assert err <= TOL_F16_ABS
