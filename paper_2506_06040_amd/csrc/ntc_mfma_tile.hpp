@@ -153,9 +153,19 @@ struct PrecF16 {
   }
 };
 
-// BF16 operands, 32x32x16 tiles (same layout as FP16). There is no BF16
-// maximum instruction, so ReLU is a median with 0 in FP32 before the packed
-// conversion.
+// BF16 operands, 32x32x16 tiles (same layout as FP16). ReLU acts on the
+// converted pair: a BF16 value is negative exactly when its sign bit is set,
+// so the signed 16-bit maximum with 0 (one packed instruction per pair)
+// zeroes the negative halves; rounding to nearest keeps the sign, so this
+// equals rounding the ReLU of the FP32 value.
+__device__ __forceinline__ bf16x2_t relu_bf16_pk(float a, float b) {
+  typedef short s16x2_t __attribute__((ext_vector_type(2)));
+  const f32x2 v = {a, b};
+  const s16x2_t h = __builtin_bit_cast(s16x2_t, __builtin_convertvector(v, bf16x2_t));
+  const s16x2_t z = {0, 0};
+  return __builtin_bit_cast(bf16x2_t, __builtin_elementwise_max(h, z));
+}
+
 struct PrecBF16 {
   using Frag = bf16x8_t;
   static constexpr int KSTEP = 16;
@@ -185,9 +195,7 @@ struct PrecBF16 {
       const int o = 8 * (c & 1);
 #pragma unroll
       for (int i = 0; i < 8; i += 2) {
-        const f32x2 p = {__builtin_amdgcn_fmed3f(v[o + i], 0.0f, 3.0e38f),
-                         __builtin_amdgcn_fmed3f(v[o + i + 1], 0.0f, 3.0e38f)};
-        const bf16x2_t h = __builtin_convertvector(p, bf16x2_t);
+        const bf16x2_t h = relu_bf16_pk(v[o + i], v[o + i + 1]);
         hb[c][i] = h[0];
         hb[c][i + 1] = h[1];
       }
