@@ -374,10 +374,12 @@ ntc_status ntc_decode_filtered(const ntc_latent_mips *lat, const ntc_mlp *mlp, c
       while ((w << e) < w0) ++e;
       if ((w << e) != w0 || (h << e) != h0) f.shared_lod = 0;
       f.lod_shift[k] = (float)e;
+      f.shift_i[k] = e;
     } else {
       while ((w0 << e) < w) ++e;
       if ((w0 << e) != w || (h0 << e) != h) f.shared_lod = 0;
       f.lod_shift[k] = -(float)e;
+      f.shift_i[k] = -e;
     }
   }
   hipError_t e = launch_decode_filtered(f, s, device_cus() * 8, (hipStream_t)stream);

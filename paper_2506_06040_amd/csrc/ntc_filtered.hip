@@ -141,13 +141,12 @@ __device__ __forceinline__ LodSel lod_select(const FilterArgs &f, int k, const L
 // base's (clamped to [-64, 64], NaN to -64): where the level's value
 // lod - e is not clamped it is exact, so its floor is fl - e and its
 // fraction fr; where it is, the first or the last mip is taken alone.
-__device__ __forceinline__ LodSel lod_select_int(const FilterArgs &f, int k, const LodBase &b, int fl, float fr,
-                                                 int e) {
+__device__ __forceinline__ LodSel lod_select_int(const FilterArgs &f, int k, const LodBase &b, int fl, float fr) {
   LodSel s;
-  const int nm = f.n_mips[k];
-  const int m = fl - e;
-  s.m0 = m < 0 ? 0 : (m > nm - 1 ? nm - 1 : m);
-  s.t = (m >= 0 && m < nm - 1) ? fr : 0.0f;
+  const int last = f.n_mips[k] - 1;
+  const int m = fl - f.shift_i[k];
+  s.m0 = min(max(m, 0), last);
+  s.t = (unsigned)m < (unsigned)last ? fr : 0.0f;  // 0 <= m < last
   s.n = b.n;
   s.du = b.du;
   s.dv = b.dv;
@@ -518,7 +517,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
           const float fr = l - fl;
 #pragma unroll
           for (int k = 0; k < kMaxLevels; ++k)
-            sel[k] = lod_select_int(f, k < f.n_levels ? k : 0, b, (int)fl, fr, (int)f.lod_shift[k]);
+            sel[k] = lod_select_int(f, k < f.n_levels ? k : 0, b, (int)fl, fr);
         } else {
 #pragma unroll
           for (int k = 0; k < kMaxLevels; ++k) sel[k] = lod_select(f, k < f.n_levels ? k : 0, b, f.lod_shift[k]);
@@ -570,10 +569,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PE
             }
             return sample_direct16(mip_level(f, k, m), tap_coord(x), tap_coord(y), 0);
           };
-          if constexpr (FILTER == 1)
-            c16[k] = trilinear16(sel[k], u, v, smp);
-          else
-            c = filter_level<FILTER>(sel[k], u, v, [&](int m, float x, float y) { return tex_f3(smp(m, x, y)); });
+          // every lane reads mip m_lo alone (blend weight 0) and it is
+          // staged: the samples take the region's values as wave-uniform
+          // parameters (the same values as smp gives them)
+          const bool lo_only = s0 && __builtin_amdgcn_ballot_w64(sel[k].m0 != mlo || sel[k].t > 0.0f) == 0;
+          auto smp_lo = [&](int, float x, float y) -> Tex16 {
+            return staged_sample(stage, fw0, fh0, cx, cy, kbw0, kb0, x, y, in0);
+          };
+          if constexpr (FILTER == 1) {
+            if (lo_only)
+              c16[k] = smp_lo(mlo, u, v);
+            else
+              c16[k] = trilinear16(sel[k], u, v, smp);
+          } else {
+            if (lo_only)
+              c = filter_level<FILTER>(sel[k], u, v,
+                                       [&](int m, float x, float y) { return tex_f3(smp_lo(m, x, y)); });
+            else
+              c = filter_level<FILTER>(sel[k], u, v, [&](int m, float x, float y) { return tex_f3(smp(m, x, y)); });
+          }
         }
         if constexpr (FILTER != 1) put_level(xl, xh, k, c);
       }

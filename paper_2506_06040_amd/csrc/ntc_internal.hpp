@@ -212,6 +212,7 @@ struct FilterArgs {
   // both axes (lod_shift[k] = e_k), so its squared footprint axes are level
   // 0's times 4^-e_k exactly and its level of detail is level 0's minus e_k
   float lod_shift[kMaxLevels];
+  int32_t shift_i[kMaxLevels];  // lod_shift as integers
   int32_t shared_lod;
   int32_t n_levels, filter, max_aniso;
 };
