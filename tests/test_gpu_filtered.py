@@ -203,3 +203,18 @@ def test_level_larger_than_level0(filt):
     print(f"[larger level 1 {filt}] left out {int((~keep).sum())} max err {err:.2e}", flush=True)
     assert (~keep).sum() <= 1e-3 * uv.shape[0]
     assert err <= TOL_F16_ABS
+
+
+@pytest.mark.parametrize("filt", ["trilinear", "anisotropic"])
+def test_f16_output_is_rounded_f32_output(filt):
+    """FP16 outputs are the FP32 outputs rounded to nearest even, bit for
+    bit (the sigmoid is evaluated in FP32 either way)."""
+    ntc = _ntc()
+    rng, chains, Ws, bs = _case(9, [(128, 128), (64, 64), (32, 32), (16, 16)])
+    uv, duv = I.perspective_plane(80, 70, far=10.0)
+    lm, mlp = ntc.LatentMips(chains, shift=I.PAPER_SHIFT), ntc.Mlp(Ws, bs)
+    uvt, duvt = torch.from_numpy(uv).cuda(), torch.from_numpy(duv * np.float32(2.0)).cuda()
+    o32 = ntc.decode_filtered(lm, mlp, uvt, duvt, filter=filt, max_aniso=8)
+    o16 = ntc.decode_filtered(lm, mlp, uvt, duvt, filter=filt, max_aniso=8, out_dtype=torch.float16)
+    assert o16.dtype == torch.float16
+    assert torch.equal(o16, o32.half())
