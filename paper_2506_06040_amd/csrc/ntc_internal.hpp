@@ -88,7 +88,7 @@ hipError_t launch_decode_plain(const DecodeArgs &a, const MlpShape &s, float *ca
 hipError_t launch_decode_mfma(const DecodeArgs &a, const MlpShape &s, int compute, int grid_waves, hipStream_t st);
 // FP32 decode of float latents on the matrix cores (up to 4 layers).
 hipError_t launch_forward_f32(const DecodeArgs &a, const MlpShape &s, hipStream_t st);
-int decode_span_tiles();  // 64-pixel tiles per span of the matrix-core decode
+int decode_span_tiles(int hid, int n_layers, int compute);  // 64-pixel tiles per span of the matrix-core decode
 hipError_t launch_bc1_texels(const LevelArgs &L, float *out, uint16_t *numer, hipStream_t st);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
 

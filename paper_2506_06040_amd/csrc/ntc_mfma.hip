@@ -4,7 +4,7 @@
 // The paper evaluates the MLP per 8x4 pixel tile on the matrix engines of its
 // GPUs through cooperative vectors, with all threads of a workgroup sharing
 // one weight matrix (Sec. 4). Here a wavefront keeps the whole MLP in
-// registers and walks spans of 256 pixels; every layer is a product of
+// registers and walks spans of 256 or 512 pixels; every layer is a product of
 // 32x32 tiles (v_mfma_f32_32x32x16_f16, or the 32x32x64 E4M3 form), the
 // full-rate matrix instructions of gfx950. The tile-level data flow is
 // described in ntc_mfma_tile.hpp.
@@ -16,12 +16,9 @@
 
 namespace ntc {
 
-// 64-pixel tiles per span (staged together).
-constexpr int kSpanTiles = NTC_SPAN_TILES;
-
 template <class P, int HID, int NL, int VEC4>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NTC_WAVES_PER_SIMD, NTC_WAVES_PER_SIMD))) void decode_mfma_kernel(DecodeArgs a) {
-  constexpr int ST = kSpanTiles;
+  constexpr int ST = span_tiles_for(HID, NL, P::kF16Tex);
   constexpr int SPX = 64 * ST;
   extern __shared__ f32x4 smem[];
   f32x4 *stage = smem;
@@ -91,11 +88,14 @@ static hipError_t launch_mfma_prec(const DecodeArgs &a, const MlpShape &s, int g
   }
 }
 
-int decode_span_tiles() { return kSpanTiles; }
+int decode_span_tiles(int hid, int n_layers, int compute) {
+  return span_tiles_for(hid, n_layers, compute == 1 ? PrecF16::kF16Tex : (compute == 2 ? PrecBF16::kF16Tex : PrecF8::kF16Tex));
+}
 
 hipError_t launch_decode_mfma(const DecodeArgs &a, const MlpShape &s, int compute, int grid_waves, hipStream_t st) {
   int64_t grid = grid_waves;
-  const int64_t n_iter = (a.n_tiles + kSpanTiles - 1) / kSpanTiles;
+  const int span = decode_span_tiles(s.hid, s.n_layers, compute);
+  const int64_t n_iter = (a.n_tiles + span - 1) / span;
   if (grid > n_iter) grid = n_iter;
   if (grid >= 8) grid &= ~(int64_t)7;
   if (grid < 1) grid = 1;

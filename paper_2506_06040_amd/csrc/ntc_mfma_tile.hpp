@@ -41,8 +41,11 @@
 #ifndef NTC_WAVES_PER_SIMD  // occupancy the register allocation is held to
 #define NTC_WAVES_PER_SIMD 2
 #endif
-#ifndef NTC_SPAN_TILES  // 64-pixel tiles staged together
+#ifndef NTC_SPAN_TILES  // 64-pixel tiles staged together (64-wide nets, 4+ layers)
 #define NTC_SPAN_TILES 4
+#endif
+#ifndef NTC_SPAN_TILES_SMALL  // the same for the other shapes
+#define NTC_SPAN_TILES_SMALL 8
 #endif
 #ifndef NTC_WIDE_NT  // N-tiles per MLP pass of 64-wide nets with hidden layers
 #define NTC_WIDE_NT 2
@@ -62,6 +65,18 @@
 #ifndef NTC_STORE_AUX  // cache policy of the output stores (2: non-temporal)
 #define NTC_STORE_AUX 2
 #endif
+
+namespace ntc {
+// 64-pixel tiles per span for an MLP shape. A longer span spreads the
+// footprint reductions, staging records and partly filled staging passes
+// over more pixels, which pays where the MLP leaves registers for the
+// longer span's coordinates; 64-wide networks keep the shorter span with
+// four or more layers (88+ VGPRs of weights and two N-tiles of
+// accumulators) and with FP32 texels (the BF16 and E4M3 decodes).
+constexpr int span_tiles_for(int hid, int n_layers, bool f16_texels) {
+  return (hid >= 64 && (n_layers >= 4 || !f16_texels)) ? NTC_SPAN_TILES : NTC_SPAN_TILES_SMALL;
+}
+}  // namespace ntc
 #ifndef NTC_UV_PREFETCH  // load the next span's uv during the current span
 #define NTC_UV_PREFETCH 1
 #endif

@@ -151,7 +151,7 @@ def test_staged_equals_direct_and_deterministic():
         c = ntc.decode(lat, mlp, uvt, compute=compute, packed=packed, cfg=ntc.tile_cfg(stage_capacity=64))
         d = ntc.decode(lat, mlp, uvt, compute=compute, packed=packed, cfg=ntc.tile_cfg(waves_per_cu=3))
         e = ntc.decode(lat, mlp, uvt, compute=compute, packed=packed, cfg=ntc.tile_cfg(waves_per_cu=1))
-        f = ntc.decode(lat, mlp, uvt[:4099], compute=compute, packed=packed, cfg=ntc.tile_cfg(tiles_per_iter=4))
+        f = ntc.decode(lat, mlp, uvt[:4099], compute=compute, packed=packed, cfg=ntc.tile_cfg(tiles_per_iter=8))
         torch.cuda.synchronize()
         assert torch.equal(a, b)
         assert torch.equal(a, c)
