@@ -22,15 +22,20 @@
 
 namespace ntc {
 
-// 64-pixel tiles per span of the batched walk: every shape takes the short
-// span here (one kernel holds all shapes, and longer spans for the small
-// ones raise its register spills: 8.5% slower on the 64-material batch).
-constexpr int kBatchSpanTiles = NTC_SPAN_TILES;
+// 64-pixel tiles per span of the batched walk. One kernel holds every
+// shape, so a longer span raises the register spills of all of them; it
+// pays only for the 16- and 32-wide networks read in order (2% on the
+// 64-material batch; with the 64-wide 3-layer ones and the indexed reads as
+// well, 8.5% slower).
+template <int HID, bool IDX>
+constexpr int batch_span_tiles() {
+  return (HID <= 32 && !IDX) ? NTC_SPAN_TILES_SMALL : NTC_SPAN_TILES;
+}
 
 template <int HID, int NL, int VEC4, bool IDX>
 __device__ __forceinline__ void run_material(const BatchMaterial &M, const BatchItem *items, int it0, int it1,
                                              f32x4 *stage, f32x4 *bias, f32x4 *ltab) {
-  constexpr int ST = kBatchSpanTiles;
+  constexpr int ST = batch_span_tiles<HID, IDX>();
   const DecodeArgs &a = M.a;
   const int lane = threadIdx.x;
   MfmaWeights<PrecF16, HID, NL> W;
