@@ -493,3 +493,30 @@ def test_extra_output_row_keeps_other_channels_bit_identical():
             assert torch.equal(o9[:, :8], o8), (compute, cfg is None)
             err = _report(f"9th channel {compute}", o9[:, 8:9].cpu().numpy(), ref9)
             assert np.all(err <= tol)
+
+
+@pytest.mark.parametrize("compute,tol", [("f16", TOL_F16_ABS), ("bf16", TOL_BF16_ABS), ("fp8", TOL_FP8_ABS)])
+def test_span_boundaries(compute, tol):
+    """Pixel counts around the 256- and 512-pixel spans (the span length
+    depends on the network shape) on coherent uv, so that the spans are
+    staged: every pixel against the oracle, nothing written past the end."""
+    ntc = _ntc()
+    rng = np.random.default_rng(31)
+    sizes = [(64, 64), (32, 32), (16, 16), (8, 8)]
+    lat_np = I.bc1_pyramid(rng, sizes)
+    uv_all = I.pixel_uv(96, 96, "tiled", jitter_rng=rng)
+    for dims in ((14, 32, 32, 8), (14, 64, 64, 8), (14, 64, 64, 64, 8)):
+        Ws, bs = I.xavier_mlp(rng, dims, bias="normal")
+        lat, mlp = _gpu_case(lat_np, Ws, bs, I.PAPER_SHIFT)
+        olat, omlp = _oracle_case(lat_np, Ws, bs, I.PAPER_SHIFT)
+        packed = None
+        if compute == "fp8":
+            packed = ntc.pack(mlp, "fp8", act_amax=ntc.calibrate_fp8(lat, mlp, torch.from_numpy(uv_all).cuda()))
+        for n in (1, 63, 65, 255, 257, 511, 513, 1025, 4099):
+            uv = np.ascontiguousarray(uv_all[:n])
+            out = torch.full((n + 5, dims[-1]), -3.0, device="cuda")
+            ntc.decode(lat, mlp, torch.from_numpy(uv).cuda(), compute=compute, packed=packed, out=out[:n])
+            got = out.cpu().numpy()
+            assert np.all(got[n:] == -3.0), (dims, n)
+            err = np.abs(got[:n].astype(np.float64) - O.decode(olat, omlp, uv))
+            assert np.all(err <= tol), (dims, n, float(err.max()))

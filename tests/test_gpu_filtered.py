@@ -218,3 +218,24 @@ def test_f16_output_is_rounded_f32_output(filt):
     o16 = ntc.decode_filtered(lm, mlp, uvt, duvt, filter=filt, max_aniso=8, out_dtype=torch.float16)
     assert o16.dtype == torch.float16
     assert torch.equal(o16, o32.half())
+
+
+@pytest.mark.parametrize("n_out", [5, 12])
+def test_output_widths(n_out):
+    """Output widths that are not 8 (not a multiple of 4, and more than 8)
+    take the other store paths of the filtered decode."""
+    ntc = _ntc()
+    sizes = [(128, 128), (64, 64), (32, 32), (16, 16)]
+    rng, chains, Ws, bs = _case(10, sizes, dims=(14, 32, 32, n_out))
+    uv, duv = I.perspective_plane(72, 40, far=10.0)
+    duv = duv * np.float32(2.0)
+    lm, mlp = ntc.LatentMips(chains, shift=I.PAPER_SHIFT), ntc.Mlp(Ws, bs)
+    for filt in ("trilinear", "anisotropic"):
+        out = ntc.decode_filtered(lm, mlp, torch.from_numpy(uv).cuda(), torch.from_numpy(duv).cuda(), filter=filt,
+                                  max_aniso=8).cpu().numpy()
+        assert out.shape == (uv.shape[0], n_out)
+        ref = F.decode(chains, I.PAPER_SHIFT, O.Mlp(Ws, bs), uv, duv, filt, 8)
+        keep = ~_ambiguous(sizes, duv, 8) if filt == "anisotropic" else np.ones(uv.shape[0], bool)
+        err = np.abs(out - ref)[keep].max()
+        assert (~keep).sum() <= 1e-3 * uv.shape[0]
+        assert err <= TOL_F16_ABS, (filt, n_out, err)
