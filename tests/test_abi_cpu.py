@@ -106,6 +106,24 @@ def test_decode_validation(A):
                                              0x1000, 0x1000, 5, 0x1000, 0, None, None) and A.lib().ntc_last_error())
 
 
+def test_span_length_per_shape(A):
+    """tiles_per_iter must name the span compiled for the network shape and
+    precision: 4 tiles for 64-wide networks of four or more layers and for
+    the 64-wide BF16 / E4M3 decodes, 8 otherwise (n = 0: validated, nothing
+    enqueued)."""
+    lat = _lat(A)
+    cfg = A.ntc_tile_cfg()
+    cases = [((14, 32, 32, 8), A.F16, 8), ((14, 64, 64, 8), A.F16, 8), ((14, 64, 64, 64, 8), A.F16, 4),
+             ((14, 64, 64, 8), A.BF16, 4), ((14, 32, 32, 8), A.BF16, 8), ((14, 64, 64, 8), A.FP8_E4M3, 4),
+             ((14, 16, 16, 16, 16, 8), A.F16, 8)]
+    for dims, compute, span in cases:
+        mlp = _mlp(A, dims=dims)
+        cfg.tiles_per_iter = span
+        assert _decode(A, lat, mlp, compute=compute, n=0, cfg=cfg) == A.OK, (dims, compute)
+        cfg.tiles_per_iter = 12 - span
+        assert _decode(A, lat, mlp, compute=compute, n=0, cfg=cfg) == A.E_UNSUPPORTED, (dims, compute)
+
+
 def test_pack_validation(A):
     L = A.lib()
     mlp = _mlp(A)
